@@ -1,0 +1,150 @@
+"""FP64 CPU oracle for the QAOA hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product library never calls it, and
+it shares no code with the GPU path: the arithmetic lives in ``oracle.c``
+(plain C, double precision, written from the paper's definitions), built with
+gcc into ``liboracle.so`` and called here through ctypes.
+
+Functions and the passages they follow:
+  diag_terms      Eq. (1): spin polynomial, term by term
+  diag_labs       Section 2, LABS: sum_k C_k^2 (direct autocorrelation form)
+  diag_maxcut     Section 2, MaxCut: minus the (weighted) cut
+  evolve          Algorithm 3 with Section 3.2's gate exp(-i beta X) per qubit
+  expectation     Section 3.1: E = sum |psi|^2 c (compensated), plus sum |psi|^2
+All functions are pinned by tests against closed forms, library routines,
+brute force and invariants (see tests/test_oracle_*.py).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (IEEE double, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-fno-fast-math", "-ffp-contract=off",
+                               _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=False)
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_diag_terms.argtypes = [ctypes.c_int, i64, P, P, P, P]
+    lib.oracle_diag_labs.argtypes = [ctypes.c_int, P]
+    lib.oracle_diag_maxcut.argtypes = [ctypes.c_int, i64, P, P, P]
+    lib.oracle_plus_state.argtypes = [ctypes.c_int, P]
+    lib.oracle_apply_phase.argtypes = [ctypes.c_int, P, ctypes.c_double, P]
+    lib.oracle_apply_rx.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, P]
+    lib.oracle_apply_mixer.argtypes = [ctypes.c_int, ctypes.c_double, P]
+    lib.oracle_qaoa_evolve.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, P]
+    lib.oracle_expectation.argtypes = [ctypes.c_int, P, P, P]
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+def diag_terms(n: int, terms) -> np.ndarray:
+    """Cost vector from Eq. (1) terms ``[(w, idx), ...]`` (0-based), float64[2^n]."""
+    w = np.ascontiguousarray([float(t[0]) for t in terms], dtype=np.float64)
+    ptr = np.zeros(len(terms) + 1, dtype=np.int64)
+    flat = []
+    for k, (_, idx) in enumerate(terms):
+        for i in idx:
+            if not 0 <= int(i) < n:
+                raise ValueError(f"term index {i} out of range for n={n}")
+            flat.append(int(i))
+        ptr[k + 1] = len(flat)
+    idx = np.ascontiguousarray(flat if flat else [0], dtype=np.int32)
+    c = np.empty(1 << n, dtype=np.float64)
+    _load().oracle_diag_terms(n, len(terms), _ptr(w), _ptr(ptr), _ptr(idx), _ptr(c))
+    return c
+
+
+def diag_labs(n: int) -> np.ndarray:
+    """LABS cost sum_k C_k^2 for every basis state, int64[2^n]."""
+    c = np.empty(1 << n, dtype=np.int64)
+    _load().oracle_diag_labs(n, _ptr(c))
+    return c
+
+
+def diag_maxcut(n: int, edges, weights=None) -> np.ndarray:
+    """Minus the weighted cut for every basis state, float64[2^n]."""
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+    if weights is None:
+        weights = np.ones(len(e))
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    c = np.empty(1 << n, dtype=np.float64)
+    _load().oracle_diag_maxcut(n, len(e), _ptr(e), _ptr(w), _ptr(c))
+    return c
+
+
+def evolve(n: int, c, gamma, beta, psi0=None) -> np.ndarray:
+    """QAOA state (Algorithm 3).  ``psi0=None`` starts from |+>^n.
+    Returns complex128[2^n]."""
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    g = np.ascontiguousarray(np.atleast_1d(gamma), dtype=np.float64)
+    b = np.ascontiguousarray(np.atleast_1d(beta), dtype=np.float64)
+    if g.shape != b.shape or c.shape != (1 << n,):
+        raise ValueError("shape mismatch")
+    psi = np.empty(1 << n, dtype=np.complex128)
+    if psi0 is not None:
+        psi[:] = psi0
+    _load().oracle_qaoa_evolve(n, len(g), _ptr(c), _ptr(g), _ptr(b),
+                               1 if psi0 is None else 0, _ptr(psi.view(np.float64)))
+    return psi
+
+
+def apply_phase(n: int, c, gamma: float, psi: np.ndarray) -> np.ndarray:
+    out = np.ascontiguousarray(psi, dtype=np.complex128).copy()
+    _load().oracle_apply_phase(n, _ptr(np.ascontiguousarray(c, dtype=np.float64)),
+                               float(gamma), _ptr(out.view(np.float64)))
+    return out
+
+
+def apply_mixer(n: int, beta: float, psi: np.ndarray) -> np.ndarray:
+    out = np.ascontiguousarray(psi, dtype=np.complex128).copy()
+    _load().oracle_apply_mixer(n, float(beta), _ptr(out.view(np.float64)))
+    return out
+
+
+def expectation(n: int, psi, c):
+    """(E, sum |psi|^2) with compensated FP64 summation."""
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    out = np.zeros(2, dtype=np.float64)
+    _load().oracle_expectation(n, _ptr(psi.view(np.float64)), _ptr(c), _ptr(out))
+    return float(out[0]), float(out[1])
+
+
+def qaoa_expectation(n: int, c, gamma, beta) -> float:
+    """Convenience: E after p layers from |+>^n."""
+    return expectation(n, evolve(n, c, gamma, beta), c)[0]

@@ -1,0 +1,186 @@
+/*
+ * oracle.c -- plain FP64 CPU reference for the QAOA hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * includes this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark load it.  It shares no code with the GPU path.
+ *
+ * Everything is computed in IEEE double precision, straight from the
+ * definitions in the paper:
+ *   - cost vector          Eq. (1) (spin polynomial), Section 2 (MaxCut, LABS)
+ *   - QAOA state           Section 2: prod_l exp(-i beta_l M) exp(-i gamma_l C) |+>^n,
+ *                          applied as in Algorithm 3 (phase, then mixer, layer 1 first)
+ *   - mixer                Section 3.2: exp(-i beta sum_i X_i) = prod_i (cos b I - i sin b X_i)
+ *   - objective            Section 3.1: E = sum_x |psi_x|^2 c_x
+ *
+ * Conventions (readings of the paper, see the design notes):
+ *   - variable i <-> bit i of the basis index x (0-based), spin s_i = 1 - 2*bit_i(x);
+ *   - the mixer gate on qubit i is cos(beta) I - i sin(beta) X_i (Section 3.2),
+ *     i.e. off-diagonal entry b = -i sin(beta) in Algorithm 1's matrix form;
+ *   - E is not renormalised; the squared norm is returned beside it.
+ *
+ * OpenMP is used on outer loops over basis states only; each output element is
+ * produced by exactly the same arithmetic as in a serial run, so results do not
+ * depend on the thread count (except the compensated sum, which is serial).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static inline double spin(uint64_t x, int i) { return ((x >> i) & 1u) ? -1.0 : 1.0; }
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Eq. (1): f(s) = sum_k w_k prod_{i in t_k} s_i, evaluated term by term with
+ * explicit spin products (no parity tricks).  Term k owns idx[ptr[k]..ptr[k+1]). */
+void oracle_diag_terms(int n, int64_t L, const double *w, const int64_t *ptr,
+                       const int32_t *idx, double *c)
+{
+    const int64_t N = (int64_t)1 << n;
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < N; ++x) {
+        double f = 0.0;
+        for (int64_t k = 0; k < L; ++k) {
+            double term = w[k];
+            for (int64_t j = ptr[k]; j < ptr[k + 1]; ++j)
+                term *= spin((uint64_t)x, idx[j]);
+            f += term;
+        }
+        c[x] = f;
+    }
+}
+
+/* LABS, direct definition: c(s) = sum_{k=1}^{n-1} C_k^2, C_k = sum_{i=0}^{n-k-1} s_i s_{i+k}.
+ * Integer arithmetic, exact. */
+void oracle_diag_labs(int n, int64_t *c)
+{
+    const int64_t N = (int64_t)1 << n;
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < N; ++x) {
+        int64_t e = 0;
+        for (int k = 1; k < n; ++k) {
+            int64_t ck = 0;
+            for (int i = 0; i + k < n; ++i) {
+                int si = ((x >> i) & 1) ? -1 : 1;
+                int sk = ((x >> (i + k)) & 1) ? -1 : 1;
+                ck += si * sk;
+            }
+            e += ck * ck;
+        }
+        c[x] = e;
+    }
+}
+
+/* Weighted MaxCut, direct definition in minimisation form (Section 2):
+ * c(x) = - sum_{(u,v) in E} w_uv [bit_u(x) != bit_v(x)]. */
+void oracle_diag_maxcut(int n, int64_t m, const int32_t *edges, const double *w, double *c)
+{
+    const int64_t N = (int64_t)1 << n;
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < N; ++x) {
+        double cut = 0.0;
+        for (int64_t e = 0; e < m; ++e) {
+            int u = edges[2 * e], v = edges[2 * e + 1];
+            if (((x >> u) & 1) != ((x >> v) & 1)) cut += w[e];
+        }
+        c[x] = -cut;
+    }
+}
+
+/* |+>^n: every amplitude 2^{-n/2}. psi is interleaved (re, im). */
+void oracle_plus_state(int n, double *psi)
+{
+    const int64_t N = (int64_t)1 << n;
+    const double a = pow(2.0, -0.5 * n);
+    for (int64_t x = 0; x < N; ++x) { psi[2 * x] = a; psi[2 * x + 1] = 0.0; }
+}
+
+/* Phase operator (Section 3.1): psi_x <- exp(-i gamma c_x) psi_x, angle = gamma * c_x. */
+void oracle_apply_phase(int n, const double *c, double gamma, double *psi)
+{
+    const int64_t N = (int64_t)1 << n;
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < N; ++x) {
+        double th = gamma * c[x];
+        double cr = cos(th), ci = -sin(th);
+        double r = psi[2 * x], i = psi[2 * x + 1];
+        psi[2 * x] = cr * r - ci * i;
+        psi[2 * x + 1] = cr * i + ci * r;
+    }
+}
+
+/* One mixer gate exp(-i beta X_q) = cos(beta) I - i sin(beta) X_q (Section 3.2) on
+ * qubit q: every basis state x with bit q clear is paired with x | 2^q and the
+ * 2x2 matrix [[cos b, -i sin b], [-i sin b, cos b]] acts on the pair
+ * (the single-qubit update of Algorithm 1). */
+void oracle_apply_rx(int n, int q, double beta, double *psi)
+{
+    const int64_t N = (int64_t)1 << n;
+    const int64_t bit = (int64_t)1 << q;
+    const double a = cos(beta), s = sin(beta);
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < N; ++x) {
+        if (x & bit) continue;
+        int64_t y = x | bit;
+        double r0 = psi[2 * x], i0 = psi[2 * x + 1];
+        double r1 = psi[2 * y], i1 = psi[2 * y + 1];
+        /* u0 = a*y0 - i s*y1 ; u1 = -i s*y0 + a*y1 */
+        psi[2 * x] = a * r0 + s * i1;
+        psi[2 * x + 1] = a * i0 - s * r1;
+        psi[2 * y] = a * r1 + s * i0;
+        psi[2 * y + 1] = a * i1 - s * r0;
+    }
+}
+
+/* Full transverse-field mixer: the gate above on every qubit (Algorithm 2). */
+void oracle_apply_mixer(int n, double beta, double *psi)
+{
+    for (int q = 0; q < n; ++q) oracle_apply_rx(n, q, beta, psi);
+}
+
+/* Algorithm 3: optional |+>^n start, then for l = 1..p the phase with gamma_l
+ * followed by the mixer with beta_l. */
+void oracle_qaoa_evolve(int n, int p, const double *c, const double *gamma,
+                        const double *beta, int init, double *psi)
+{
+    if (init) oracle_plus_state(n, psi);
+    for (int l = 0; l < p; ++l) {
+        oracle_apply_phase(n, c, gamma[l], psi);
+        oracle_apply_mixer(n, beta[l], psi);
+    }
+}
+
+/* Neumaier-compensated summation step. */
+static inline void neumaier_add(double *sum, double *comp, double v)
+{
+    double t = *sum + v;
+    if (fabs(*sum) >= fabs(v)) *comp += (*sum - t) + v;
+    else *comp += (v - t) + *sum;
+    *sum = t;
+}
+
+/* Objective (Section 3.1): out[0] = sum_x |psi_x|^2 c_x, out[1] = sum_x |psi_x|^2,
+ * both with compensated summation in index order. */
+void oracle_expectation(int n, const double *psi, const double *c, double *out)
+{
+    const int64_t N = (int64_t)1 << n;
+    double e = 0.0, ec = 0.0, q = 0.0, qc = 0.0;
+    for (int64_t x = 0; x < N; ++x) {
+        double pr = psi[2 * x] * psi[2 * x] + psi[2 * x + 1] * psi[2 * x + 1];
+        neumaier_add(&e, &ec, pr * c[x]);
+        neumaier_add(&q, &qc, pr);
+    }
+    out[0] = e + ec;
+    out[1] = q + qc;
+}
