@@ -1,0 +1,179 @@
+/*
+ * qaoa.h -- C ABI of libqaoa.so, a QAOA state-vector simulator for AMD MI355X
+ * (gfx950).  It implements the hot path of "Fast Simulation of High-Depth QAOA
+ * Circuits" (arXiv:2309.04841):
+ *
+ *   1. precompute the diagonal cost vector c[x] for all 2^n basis states from
+ *      weighted spin terms (Eq. (1); Section 3.1);
+ *   2. evolve the state through p layers of the phase exp(-i gamma_l c) and the
+ *      transverse-field mixer prod_i exp(-i beta_l X_i) (Algorithm 3; the gate is
+ *      cos(beta) I - i sin(beta) X as written in Section 3.2);
+ *   3. evaluate E = sum_x |psi_x|^2 c_x (Section 3.1).
+ *
+ * Conventions.
+ *   - Variable i (0-based) is bit i of the basis index x; spin s_i = 1 - 2*bit_i(x).
+ *   - States are interleaved complex numbers (re, im): complex128 = 2 x double,
+ *     complex64 = 2 x float.  2^n elements, index x at element x.
+ *   - Cost vectors have 2^n elements of one of the diag dtypes below.  The value
+ *     used by the simulator is  c[x] = stored[x] + diag_offset  (the offset is
+ *     0 for F64 and I32 as produced by qaoa_precompute_diag; U16 needs one).
+ *   - Layer order follows Algorithm 3: layer 1 first, phase before mixer.
+ *
+ * Memory and streams.
+ *   - Every device buffer (state, cost vector, workspace, outputs) is allocated
+ *     and owned by the caller; the library allocates nothing.  Sizes are passed
+ *     in and checked.  qaoa_workspace_bytes() gives workspace sizes.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  qaoa_evolve and
+ *     qaoa_expectation only enqueue work and never synchronise; results land in
+ *     device memory.  qaoa_precompute_diag may synchronise `stream` once, to read
+ *     back a range check (documented below).
+ *   - Calls on different streams that touch the same buffers race; so do calls
+ *     that share one workspace buffer concurrently.
+ *
+ * Errors.  Every entry point validates all arguments before enqueuing anything
+ * and returns a qaoa_status; on failure nothing has been enqueued (except where
+ * noted for device errors), and qaoa_last_error() returns a message for the
+ * calling thread.  The library never aborts and is safe to call from several
+ * host threads.
+ */
+#ifndef QAOA_H
+#define QAOA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+    QAOA_OK = 0,
+    QAOA_ERR_INVALID = 1,     /* bad argument: size, pointer, index, non-finite value */
+    QAOA_ERR_RANGE = 2,       /* cost values not representable in the requested dtype */
+    QAOA_ERR_NOMEM = 3,       /* a caller-provided buffer is too small */
+    QAOA_ERR_DEVICE = 4,      /* HIP runtime or launch failure (message has the HIP error) */
+    QAOA_ERR_UNSUPPORTED = 5  /* valid request this build does not implement */
+};
+
+/* State dtypes (interleaved complex). */
+enum { QAOA_C64 = 0, QAOA_C128 = 1 };
+
+/* Cost-vector dtypes. */
+enum { QAOA_DIAG_F64 = 0, QAOA_DIAG_I32 = 1, QAOA_DIAG_U16 = 2 };
+
+/* Operations for qaoa_workspace_bytes. */
+enum { QAOA_OP_PRECOMPUTE = 0, QAOA_OP_EVOLVE = 1, QAOA_OP_EXPECTATION = 2, QAOA_OP_GRAD = 3 };
+
+/* Largest qubit count accepted (2^34 complex64 amplitudes = 128 GiB). */
+#define QAOA_MAX_QUBITS 34
+
+/* Library version string, e.g. "0.1.0". Never NULL. */
+const char *qaoa_version(void);
+
+/* Message describing the last failing call made by this host thread ("" if none). */
+const char *qaoa_last_error(void);
+
+/* Workspace size in bytes that `op` needs for n qubits with the given dtypes
+ * (for QAOA_OP_PRECOMPUTE: the worst case over all term sets).  Writes *bytes.
+ * Returns QAOA_ERR_INVALID for bad arguments. */
+int qaoa_workspace_bytes(int op, int n, int state_dtype, int diag_dtype, size_t *bytes);
+
+/*
+ * qaoa_precompute_diag -- cost vector from weighted spin terms (Eq. (1),
+ * Section 3.1): c[x] = sum_k w_k prod_{i in t_k} s_i(x).
+ *
+ *   n           number of variables, 1 <= n <= QAOA_MAX_QUBITS
+ *   num_terms   L >= 0
+ *   w           host, L weights (finite)
+ *   term_ptr    host, L+1 offsets (CSR): term k owns term_idx[term_ptr[k] .. term_ptr[k+1]);
+ *               term_ptr[0] = 0, non-decreasing.  An empty term is a constant.
+ *   term_idx    host, term_ptr[L] variable indices, each 0 <= i < n (may be NULL if
+ *               term_ptr[L] == 0).  A repeated index cancels (s_i^2 = 1).
+ *   diag_dtype  QAOA_DIAG_F64 | QAOA_DIAG_I32 | QAOA_DIAG_U16
+ *   d_diag      device, 2^n elements of diag_dtype (diag_bytes >= 2^n * size)
+ *   out_offset  host, receives the offset such that c[x] = d_diag[x] + *out_offset
+ *               (0 for F64 and I32)
+ *   d_work      device workspace of work_bytes (may be NULL if work_bytes == 0).
+ *               Only U16 with non-integer weights or 2*sum|w| >= 2^16 uses the
+ *               2^n * 4-byte scratch; I32 with non-integer (dyadic) weights uses a
+ *               few KiB.
+ *   stream      hipStream_t
+ *
+ * Host arrays are only read during the call.  F64: exact for dyadic weights (else
+ * rounding differs from a term-by-term sum by O(eps * sum|w|)).  I32/U16: weights
+ * must be dyadic rationals (w * 2^k integral for some k <= 20) and every c[x] an
+ * integer that fits the dtype (U16: max - min < 2^16); otherwise QAOA_ERR_RANGE.
+ * Paths that need that check synchronise `stream` once; on QAOA_ERR_RANGE the
+ * contents of d_diag are unspecified.
+ */
+int qaoa_precompute_diag(int n, int64_t num_terms, const double *w, const int64_t *term_ptr,
+                         const int32_t *term_idx, int diag_dtype, void *d_diag, size_t diag_bytes,
+                         double *out_offset, void *d_work, size_t work_bytes, void *stream);
+
+/*
+ * qaoa_evolve -- Algorithm 3: for l = 1..p, psi <- exp(-i gamma_l c) psi, then
+ * psi <- prod_{i<n} exp(-i beta_l X_i) psi.  In place on d_state.
+ *
+ *   n, p        1 <= n <= QAOA_MAX_QUBITS, p >= 0
+ *   gamma, beta host, p finite angles each (may be NULL if p == 0)
+ *   d_diag      device cost vector (2^n of diag_dtype, diag_bytes), c = stored + diag_offset;
+ *               diag_offset must be integral for U16 and I32 so c stays an integer
+ *   d_state     device state, 2^n elements of state_dtype (state_bytes)
+ *   init        1: start from |+>^n (d_state is only written);
+ *               0: start from the contents of d_state
+ *   d_out       device, nullable: receives d_out[0] = E = sum |psi|^2 c and
+ *               d_out[1] = sum |psi|^2 of the final state (FP64, no renormalisation)
+ *   d_work      device workspace, >= qaoa_workspace_bytes(QAOA_OP_EVOLVE, ...) bytes
+ *               when d_out != NULL (may be NULL otherwise)
+ *
+ * Phase angles are formed as gamma_l * c[x] in double precision for both state
+ * dtypes; complex64 states are updated in double precision and rounded to float
+ * when stored.  Results are deterministic (fixed reduction order).
+ */
+int qaoa_evolve(int n, int p, const double *gamma, const double *beta,
+                const void *d_diag, int diag_dtype, double diag_offset, size_t diag_bytes,
+                void *d_state, int state_dtype, size_t state_bytes, int init,
+                double *d_out, void *d_work, size_t work_bytes, void *stream);
+
+/*
+ * qaoa_expectation -- E = sum_x |psi_x|^2 c_x and sum_x |psi_x|^2 (Section 3.1),
+ * accumulated in FP64 with a fixed reduction order.  Any cost vector of the
+ * right length may be passed (it need not be the one used for evolution).
+ * The state is not modified.  d_out: device, 2 doubles.
+ */
+int qaoa_expectation(int n, const void *d_state, int state_dtype, size_t state_bytes,
+                     const void *d_diag, int diag_dtype, double diag_offset, size_t diag_bytes,
+                     double *d_out, void *d_work, size_t work_bytes, void *stream);
+
+/*
+ * qaoa_grad -- E and its gradient with respect to gamma[0..p) and beta[0..p)
+ * by reverse-mode evolution (adjoint method).  d_out receives 1 + 2p doubles:
+ * E, dE/dgamma[0..p), dE/dbeta[0..p).  d_state and d_adj are two caller-owned
+ * state buffers (each 2^n elements of state_dtype); on return d_state holds the
+ * forward state at layer p.  This build returns QAOA_ERR_UNSUPPORTED after
+ * validating the arguments.
+ */
+int qaoa_grad(int n, int p, const double *gamma, const double *beta,
+              const void *d_diag, int diag_dtype, double diag_offset, size_t diag_bytes,
+              void *d_state, void *d_adj, int state_dtype, size_t state_bytes,
+              double *d_out, void *d_work, size_t work_bytes, void *stream);
+
+/*
+ * qaoa_plan_describe -- diagnostic: the HBM sweep plan qaoa_evolve uses for n
+ * qubits of state_dtype (the same planner lays out the precompute transform for
+ * an element size of elem_bytes when state_dtype < 0).  Writes up to `cap` ints:
+ *   [0] number of sweeps S, [1] register bits per thread EB, [2] 1 if the whole
+ *   vector is one tile (all layers in one launch), then per sweep:
+ *   tb, P, q0, w_store, nchunks, and nchunks triples (w, jlo, jhi).
+ * Tile bits [0,P) are global bits [0,P); tile bits [P,tb) are global bits
+ * [q0, q0+tb-P); a chunk butterflies tile bits [w+jlo, w+jhi).
+ * Returns the number of ints needed (may exceed cap), or -QAOA_ERR_INVALID.
+ */
+int qaoa_plan_describe(int n, int state_dtype, int elem_bytes, int *out, int cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QAOA_H */

@@ -9,6 +9,7 @@ gcc into ``liboracle.so`` and called here through ctypes.
 Functions and the passages they follow:
   diag_terms      Eq. (1): spin polynomial, term by term
   diag_labs       Section 2, LABS: sum_k C_k^2 (direct autocorrelation form)
+  diag_labs_at    the same at selected basis states (sampled checks)
   diag_maxcut     Section 2, MaxCut: minus the (weighted) cut
   evolve          Algorithm 3 with Section 3.2's gate exp(-i beta X) per qubit
   expectation     Section 3.1: E = sum |psi|^2 c (compensated), plus sum |psi|^2
@@ -52,6 +53,7 @@ def _load():
     lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_diag_terms.argtypes = [ctypes.c_int, i64, P, P, P, P]
     lib.oracle_diag_labs.argtypes = [ctypes.c_int, P]
+    lib.oracle_diag_labs_at.argtypes = [ctypes.c_int, i64, P, P]
     lib.oracle_diag_maxcut.argtypes = [ctypes.c_int, i64, P, P, P]
     lib.oracle_plus_state.argtypes = [ctypes.c_int, P]
     lib.oracle_apply_phase.argtypes = [ctypes.c_int, P, ctypes.c_double, P]
@@ -94,6 +96,14 @@ def diag_labs(n: int) -> np.ndarray:
     c = np.empty(1 << n, dtype=np.int64)
     _load().oracle_diag_labs(n, _ptr(c))
     return c
+
+
+def diag_labs_at(n: int, xs) -> np.ndarray:
+    """LABS cost at the given basis states only, int64."""
+    xs = np.ascontiguousarray(xs, dtype=np.int64)
+    out = np.empty(len(xs), dtype=np.int64)
+    _load().oracle_diag_labs_at(n, len(xs), _ptr(xs), _ptr(out))
+    return out
 
 
 def diag_maxcut(n: int, edges, weights=None) -> np.ndarray:

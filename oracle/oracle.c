@@ -82,6 +82,27 @@ void oracle_diag_labs(int n, int64_t *c)
     }
 }
 
+/* LABS at selected basis states only (same definition as above), for sampled
+ * checks at sizes where the full vector is too large to enumerate. */
+void oracle_diag_labs_at(int n, int64_t m, const int64_t *xs, int64_t *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < m; ++j) {
+        const int64_t x = xs[j];
+        int64_t e = 0;
+        for (int k = 1; k < n; ++k) {
+            int64_t ck = 0;
+            for (int i = 0; i + k < n; ++i) {
+                int si = ((x >> i) & 1) ? -1 : 1;
+                int sk = ((x >> (i + k)) & 1) ? -1 : 1;
+                ck += si * sk;
+            }
+            e += ck * ck;
+        }
+        out[j] = e;
+    }
+}
+
 /* Weighted MaxCut, direct definition in minimisation form (Section 2):
  * c(x) = - sum_{(u,v) in E} w_uv [bit_u(x) != bit_v(x)]. */
 void oracle_diag_maxcut(int n, int64_t m, const int32_t *edges, const double *w, double *c)

@@ -1,0 +1,217 @@
+"""ctypes binding of libqaoa.so (include/qaoa.h).
+
+Argument marshalling only: torch tensors supply device pointers and the
+current HIP stream; every step of the computation runs in the library's HIP
+kernels.  If the library is not built the import of this module fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads the HIP runtime the library binds to
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqaoa.so")
+
+QAOA_OK, QAOA_ERR_INVALID, QAOA_ERR_RANGE, QAOA_ERR_NOMEM, QAOA_ERR_DEVICE, QAOA_ERR_UNSUPPORTED = range(6)
+QAOA_C64, QAOA_C128 = 0, 1
+QAOA_DIAG_F64, QAOA_DIAG_I32, QAOA_DIAG_U16 = 0, 1, 2
+QAOA_OP_PRECOMPUTE, QAOA_OP_EVOLVE, QAOA_OP_EXPECTATION, QAOA_OP_GRAD = range(4)
+QAOA_MAX_QUBITS = 34
+
+EXPORTS = ("qaoa_version", "qaoa_last_error", "qaoa_workspace_bytes", "qaoa_precompute_diag",
+           "qaoa_evolve", "qaoa_expectation", "qaoa_grad", "qaoa_plan_describe")
+
+_STATUS_NAMES = {0: "QAOA_OK", 1: "QAOA_ERR_INVALID", 2: "QAOA_ERR_RANGE", 3: "QAOA_ERR_NOMEM",
+                 4: "QAOA_ERR_DEVICE", 5: "QAOA_ERR_UNSUPPORTED"}
+
+
+class QaoaError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python paper_2309_04841_amd/build.py` "
+                          "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, D, I, I64, SZ = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
+    lib.qaoa_version.restype = ctypes.c_char_p
+    lib.qaoa_version.argtypes = []
+    lib.qaoa_last_error.restype = ctypes.c_char_p
+    lib.qaoa_last_error.argtypes = []
+    lib.qaoa_workspace_bytes.restype = I
+    lib.qaoa_workspace_bytes.argtypes = [I, I, I, I, ctypes.POINTER(SZ)]
+    lib.qaoa_precompute_diag.restype = I
+    lib.qaoa_precompute_diag.argtypes = [I, I64, P, P, P, I, P, SZ, ctypes.POINTER(D), P, SZ, P]
+    lib.qaoa_evolve.restype = I
+    lib.qaoa_evolve.argtypes = [I, I, P, P, P, I, D, SZ, P, I, SZ, I, P, P, SZ, P]
+    lib.qaoa_expectation.restype = I
+    lib.qaoa_expectation.argtypes = [I, P, I, SZ, P, I, D, SZ, P, P, SZ, P]
+    lib.qaoa_grad.restype = I
+    lib.qaoa_grad.argtypes = [I, I, P, P, P, I, D, SZ, P, P, I, SZ, P, P, SZ, P]
+    lib.qaoa_plan_describe.restype = I
+    lib.qaoa_plan_describe.argtypes = [I, I, I, P, I]
+    return lib
+
+
+lib = _load()
+
+
+def check(status: int) -> None:
+    if status != QAOA_OK:
+        raise QaoaError(status, lib.qaoa_last_error().decode())
+
+
+def version() -> str:
+    return lib.qaoa_version().decode()
+
+
+# --------------------------------------------------------------------------
+# dtype helpers
+# --------------------------------------------------------------------------
+_STATE_DT = {torch.complex64: QAOA_C64, torch.complex128: QAOA_C128}
+_DIAG_DT = {torch.float64: QAOA_DIAG_F64, torch.int32: QAOA_DIAG_I32, torch.uint16: QAOA_DIAG_U16}
+_DIAG_TORCH = {QAOA_DIAG_F64: torch.float64, QAOA_DIAG_I32: torch.int32, QAOA_DIAG_U16: torch.uint16}
+DIAG_NAMES = {"f64": QAOA_DIAG_F64, "i32": QAOA_DIAG_I32, "u16": QAOA_DIAG_U16}
+
+
+def state_dtype_code(t: torch.Tensor) -> int:
+    try:
+        return _STATE_DT[t.dtype]
+    except KeyError:
+        raise TypeError(f"state must be complex64 or complex128, got {t.dtype}") from None
+
+
+def diag_dtype_code(t: torch.Tensor) -> int:
+    try:
+        return _DIAG_DT[t.dtype]
+    except KeyError:
+        raise TypeError(f"cost vector must be float64, int32 or uint16, got {t.dtype}") from None
+
+
+def _dev_ptr(t: torch.Tensor | None) -> int | None:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _nbytes(t: torch.Tensor) -> int:
+    return t.numel() * t.element_size()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _f64(values) -> ctypes.Array:
+    vals = [float(v) for v in values]
+    return (ctypes.c_double * max(1, len(vals)))(*vals)
+
+
+def plan_describe(n: int, state_dtype: int = QAOA_C128, elem_bytes: int = 0) -> dict:
+    """The sweep plan as a dict: {'eb', 'single', 'sweeps': [{'tb','P','q0','w_store','chunks'}]}."""
+    need = lib.qaoa_plan_describe(n, state_dtype, elem_bytes, None, 0)
+    if need < 0:
+        check(-need)
+    buf = (ctypes.c_int * need)()
+    lib.qaoa_plan_describe(n, state_dtype, elem_bytes, buf, need)
+    v = list(buf)
+    ns, eb, single = v[0], v[1], v[2]
+    i = 3
+    sweeps = []
+    for _ in range(ns):
+        tb, P, q0, ws, nc = v[i:i + 5]
+        i += 5
+        chunks = [tuple(v[i + 3 * c:i + 3 * c + 3]) for c in range(nc)]
+        i += 3 * nc
+        sweeps.append(dict(tb=tb, P=P, q0=q0, w_store=ws, chunks=chunks))
+    return dict(eb=eb, single=bool(single), sweeps=sweeps)
+
+
+def workspace_bytes(op: int, n: int, state_dtype: int = QAOA_C128, diag_dtype: int = QAOA_DIAG_I32) -> int:
+    out = ctypes.c_size_t(0)
+    check(lib.qaoa_workspace_bytes(op, n, state_dtype, diag_dtype, ctypes.byref(out)))
+    return int(out.value)
+
+
+def alloc_workspace(op: int, n: int, state_dtype: int, diag_dtype: int, device) -> torch.Tensor:
+    nb = workspace_bytes(op, n, state_dtype, diag_dtype)
+    return torch.empty(max(nb, 16), dtype=torch.uint8, device=device)
+
+
+# --------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+# --------------------------------------------------------------------------
+def qaoa_precompute_diag(n: int, terms, diag_dtype: str | int = "i32", device="cuda",
+                         work: torch.Tensor | None = None):
+    """Cost vector for Eq. (1) terms ``[(w, idx), ...]``; returns ``(diag, offset)``
+    with ``c = diag + offset``."""
+    code = DIAG_NAMES[diag_dtype] if isinstance(diag_dtype, str) else int(diag_dtype)
+    w = [float(t[0]) for t in terms]
+    ptr = [0]
+    flat = []
+    for _, idx in terms:
+        flat.extend(int(i) for i in idx)
+        ptr.append(len(flat))
+    w_arr = _f64(w)
+    ptr_arr = (ctypes.c_int64 * len(ptr))(*ptr)
+    idx_arr = (ctypes.c_int32 * max(1, len(flat)))(*flat) if flat else None
+    diag = torch.empty(1 << n, dtype=_DIAG_TORCH[code], device=device)
+    if work is None:
+        work = alloc_workspace(QAOA_OP_PRECOMPUTE, n, QAOA_C128, code, diag.device)
+    off = ctypes.c_double(0.0)
+    check(lib.qaoa_precompute_diag(n, len(terms), w_arr, ptr_arr, idx_arr, code, _dev_ptr(diag), _nbytes(diag),
+                                   ctypes.byref(off), _dev_ptr(work), _nbytes(work), _stream(diag.device)))
+    return diag, float(off.value)
+
+
+def qaoa_evolve(n: int, gamma, beta, diag: torch.Tensor, state: torch.Tensor, init: bool = True,
+                diag_offset: float = 0.0, out: torch.Tensor | None = None,
+                work: torch.Tensor | None = None) -> None:
+    """Algorithm 3 in place on ``state``; if ``out`` (float64[2], device) is given
+    it receives (E, sum |psi|^2)."""
+    p = len(gamma)
+    if len(beta) != p:
+        raise ValueError("gamma and beta differ in length")
+    sdt, ddt = state_dtype_code(state), diag_dtype_code(diag)
+    if out is not None and work is None:
+        work = alloc_workspace(QAOA_OP_EVOLVE, n, sdt, ddt, state.device)
+    check(lib.qaoa_evolve(n, p, _f64(gamma), _f64(beta), _dev_ptr(diag), ddt, float(diag_offset), _nbytes(diag),
+                          _dev_ptr(state), sdt, _nbytes(state), 1 if init else 0, _dev_ptr(out),
+                          _dev_ptr(work), 0 if work is None else _nbytes(work), _stream(state.device)))
+
+
+def qaoa_expectation(n: int, state: torch.Tensor, diag: torch.Tensor, diag_offset: float = 0.0,
+                     out: torch.Tensor | None = None, work: torch.Tensor | None = None) -> torch.Tensor:
+    """(E, sum |psi|^2) as a float64[2] device tensor."""
+    sdt, ddt = state_dtype_code(state), diag_dtype_code(diag)
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=state.device)
+    if work is None:
+        work = alloc_workspace(QAOA_OP_EXPECTATION, n, sdt, ddt, state.device)
+    check(lib.qaoa_expectation(n, _dev_ptr(state), sdt, _nbytes(state), _dev_ptr(diag), ddt, float(diag_offset),
+                               _nbytes(diag), _dev_ptr(out), _dev_ptr(work), _nbytes(work), _stream(state.device)))
+    return out
+
+
+def qaoa_grad(n: int, gamma, beta, diag: torch.Tensor, state: torch.Tensor, adj: torch.Tensor,
+              diag_offset: float = 0.0, out: torch.Tensor | None = None,
+              work: torch.Tensor | None = None) -> torch.Tensor:
+    p = len(gamma)
+    sdt, ddt = state_dtype_code(state), diag_dtype_code(diag)
+    if out is None:
+        out = torch.empty(1 + 2 * p, dtype=torch.float64, device=state.device)
+    if work is None:
+        work = alloc_workspace(QAOA_OP_GRAD, n, sdt, ddt, state.device)
+    check(lib.qaoa_grad(n, p, _f64(gamma), _f64(beta), _dev_ptr(diag), ddt, float(diag_offset), _nbytes(diag),
+                        _dev_ptr(state), _dev_ptr(adj), sdt, _nbytes(state), _dev_ptr(out), _dev_ptr(work),
+                        _nbytes(work), _stream(state.device)))
+    return out

@@ -1,0 +1,411 @@
+// kernels.hpp -- HIP kernels of the QAOA hot path for gfx950 (CDNA4, wave64).
+//
+//   qaoa_sweep_kernel   fused tile sweep: [|+> init | load] -> per layer
+//                       {phase exp(-i g c) (Section 3.1), mixer gates
+//                       cos(b) I - i sin(b) X on the tile's active qubits
+//                       (Section 3.2, Algorithms 1-2)} -> [E partials] -> store
+//   fwht_sweep_kernel   same tiling, butterfly (u, v) -> (u + v, u - v): the
+//                       unnormalised Walsh-Hadamard transform that turns the
+//                       sparse term weights into the cost vector (Eq. (1))
+//   expectation_kernel  E = sum |psi|^2 c and sum |psi|^2 (Section 3.1), FP64
+//   finalize_kernel     fixed-order sum of per-block partials
+//   helpers             fill, scatter, integer range check, narrowing
+//
+// All reductions have a fixed order (no atomics), so results are bitwise
+// reproducible run to run.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tile.hpp"
+
+namespace qk {
+
+constexpr int kMaxLayersPerLaunch = 32;
+constexpr int kScatterChunk = 240;
+
+enum : int { F_INIT = 1, F_PHASE = 2, F_EXPV = 4 };
+
+// ----------------------------------------------------------------------------
+// element policies
+// ----------------------------------------------------------------------------
+struct C128 {  // complex128: (double re, double im)
+  using L = double2;
+  static constexpr int kBytes = 16;
+  __device__ static __forceinline__ void load(const void* p, uint64_t x, double& r, double& i) {
+    const double2 v = reinterpret_cast<const double2*>(p)[x];
+    r = v.x; i = v.y;
+  }
+  __device__ static __forceinline__ void store(void* p, uint64_t x, double r, double i) {
+    reinterpret_cast<double2*>(p)[x] = make_double2(r, i);
+  }
+  __device__ static __forceinline__ void lput(L* s, uint32_t pos, double r, double i) { s[pos] = make_double2(r, i); }
+  __device__ static __forceinline__ void lget(const L* s, uint32_t pos, double& r, double& i) {
+    const double2 v = s[pos];
+    r = v.x; i = v.y;
+  }
+};
+
+struct C64 {  // complex64 storage, FP64 arithmetic in registers
+  using L = float2;
+  static constexpr int kBytes = 8;
+  __device__ static __forceinline__ void load(const void* p, uint64_t x, double& r, double& i) {
+    const float2 v = reinterpret_cast<const float2*>(p)[x];
+    r = (double)v.x; i = (double)v.y;
+  }
+  __device__ static __forceinline__ void store(void* p, uint64_t x, double r, double i) {
+    reinterpret_cast<float2*>(p)[x] = make_float2((float)r, (float)i);
+  }
+  __device__ static __forceinline__ void lput(L* s, uint32_t pos, double r, double i) {
+    s[pos] = make_float2((float)r, (float)i);
+  }
+  __device__ static __forceinline__ void lget(const L* s, uint32_t pos, double& r, double& i) {
+    const float2 v = s[pos];
+    r = (double)v.x; i = (double)v.y;
+  }
+};
+
+struct DI32 {
+  __device__ static __forceinline__ double get(const void* p, uint64_t x) {
+    return (double)reinterpret_cast<const int32_t*>(p)[x];
+  }
+};
+struct DU16 {
+  __device__ static __forceinline__ double get(const void* p, uint64_t x) {
+    return (double)reinterpret_cast<const uint16_t*>(p)[x];
+  }
+};
+struct DF64 {
+  __device__ static __forceinline__ double get(const void* p, uint64_t x) {
+    return reinterpret_cast<const double*>(p)[x];
+  }
+};
+
+// ----------------------------------------------------------------------------
+// reductions
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sums (x, y) over the workgroup in a fixed order; result valid in thread 0.
+// `scratch` holds 2 doubles per wave (2 per thread when the workgroup is a
+// single partial wave).  Ends with all threads past a barrier.
+__device__ __forceinline__ void block_sum2(double& x, double& y, double* scratch) {
+  if (blockDim.x < 64) {
+    // partial wave: no cross-lane shuffles over inactive lanes
+    scratch[2 * threadIdx.x] = x;
+    scratch[2 * threadIdx.x + 1] = y;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sx = 0.0, sy = 0.0;
+      for (uint32_t i = 0; i < blockDim.x; ++i) { sx += scratch[2 * i]; sy += scratch[2 * i + 1]; }
+      x = sx; y = sy;
+    }
+    __syncthreads();
+    return;
+  }
+  x = wave_sum(x);
+  y = wave_sum(y);
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  if (lane == 0) { scratch[2 * wv] = x; scratch[2 * wv + 1] = y; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t nw = (blockDim.x + 63u) >> 6;
+    double sx = 0.0, sy = 0.0;
+    for (uint32_t i = 0; i < nw; ++i) { sx += scratch[2 * i]; sy += scratch[2 * i + 1]; }
+    x = sx; y = sy;
+  }
+  __syncthreads();
+}
+
+// ----------------------------------------------------------------------------
+// fused QAOA sweep
+// ----------------------------------------------------------------------------
+struct SweepArgs {
+  void* psi;
+  const void* diag;
+  double* partials;   // 2 doubles per block (E, norm) when F_EXPV
+  double diag_offset;
+  double amp0;        // 2^{-n/2} for F_INIT
+  int flags;
+  int nlayers;        // layers applied by this launch
+  TileGeom g;
+  double gamma[kMaxLayersPerLaunch];
+  double ca[kMaxLayersPerLaunch];  // cos(beta_l)
+  double sb[kMaxLayersPerLaunch];  // sin(beta_l)
+};
+
+// gate cos(b) I - i sin(b) X on the pair (y0, y1):
+//   y0' = a y0 - i s y1,  y1' = -i s y0 + a y1
+__device__ __forceinline__ void rx_pair(double& r0, double& i0, double& r1, double& i1, double a, double s) {
+  const double nr0 = fma(a, r0, s * i1);
+  const double ni0 = fma(a, i0, -s * r1);
+  const double nr1 = fma(a, r1, s * i0);
+  const double ni1 = fma(a, i1, -s * r0);
+  r0 = nr0; i0 = ni0; r1 = nr1; i1 = ni1;
+}
+
+template <class S, int EB>
+__device__ __forceinline__ void exchange_c(double (&vr)[1 << EB], double (&vi)[1 << EB], typename S::L* lds,
+                                           uint32_t tid, int wf, int wt) {
+#pragma unroll
+  for (int k = 0; k < (1 << EB); ++k) S::lput(lds, swz<S::kBytes>(tmap<EB>(tid, k, wf)), vr[k], vi[k]);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < (1 << EB); ++k) S::lget(lds, swz<S::kBytes>(tmap<EB>(tid, k, wt)), vr[k], vi[k]);
+  __syncthreads();
+}
+
+template <class S, class D, int EB>
+__global__ void __launch_bounds__(512) qaoa_sweep_kernel(const SweepArgs a) {
+  constexpr int E = 1 << EB;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  typename S::L* lds = reinterpret_cast<typename S::L*>(smem_raw);
+  const uint32_t tid = threadIdx.x;
+  const int P = a.g.P, q0 = a.g.q0;
+  const uint64_t base = block_base(blockIdx.x, a.g.tb, P, q0);
+
+  double vr[E], vi[E];
+  int w = a.g.tb - EB;
+  if (a.flags & F_INIT) {
+#pragma unroll
+    for (int k = 0; k < E; ++k) { vr[k] = a.amp0; vi[k] = 0.0; }
+  } else {
+#pragma unroll
+    for (int k = 0; k < E; ++k) S::load(a.psi, base + tile_off(tmap<EB>(tid, k, w), P, q0), vr[k], vi[k]);
+  }
+
+  for (int l = 0; l < a.nlayers; ++l) {
+    if (a.flags & F_PHASE) {
+      const double g = a.gamma[l];
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const uint64_t x = base + tile_off(tmap<EB>(tid, k, w), P, q0);
+        const double c = D::get(a.diag, x) + a.diag_offset;
+        double sn, cs;
+        sincos(g * c, &sn, &cs);
+        // multiply by exp(-i g c) = cs - i sn
+        const double r = vr[k], im = vi[k];
+        vr[k] = fma(cs, r, sn * im);
+        vi[k] = fma(cs, im, -sn * r);
+      }
+    }
+    const double ca = a.ca[l], sb = a.sb[l];
+    for (int ci = 0; ci < a.g.nchunks; ++ci) {
+      const Chunk ch = a.g.chunk[ci];
+      if (ch.w != w) {
+        exchange_c<S, EB>(vr, vi, lds, tid, w, ch.w);
+        w = ch.w;
+      }
+#pragma unroll
+      for (int j = 0; j < EB; ++j) {
+        if (j >= ch.jlo && j < ch.jhi) {
+#pragma unroll
+          for (int k = 0; k < E; ++k) {
+            if (!(k & (1 << j))) rx_pair(vr[k], vi[k], vr[k | (1 << j)], vi[k | (1 << j)], ca, sb);
+          }
+        }
+      }
+    }
+  }
+
+  double e_part = 0.0, n_part = 0.0;
+  if (a.flags & F_EXPV) {
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const uint64_t x = base + tile_off(tmap<EB>(tid, k, w), P, q0);
+      const double c = D::get(a.diag, x) + a.diag_offset;
+      const double pr = vr[k] * vr[k] + vi[k] * vi[k];
+      e_part += pr * c;
+      n_part += pr;
+    }
+  }
+
+  if (w != a.g.w_store) {
+    exchange_c<S, EB>(vr, vi, lds, tid, w, a.g.w_store);
+    w = a.g.w_store;
+  }
+#pragma unroll
+  for (int k = 0; k < E; ++k) S::store(a.psi, base + tile_off(tmap<EB>(tid, k, w), P, q0), vr[k], vi[k]);
+
+  if (a.flags & F_EXPV) {
+    block_sum2(e_part, n_part, reinterpret_cast<double*>(smem_raw));
+    if (tid == 0) {
+      a.partials[2 * (uint64_t)blockIdx.x] = e_part;
+      a.partials[2 * (uint64_t)blockIdx.x + 1] = n_part;
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Walsh-Hadamard sweep for the cost-vector precompute
+// ----------------------------------------------------------------------------
+struct FwhtArgs {
+  void* data;
+  TileGeom g;
+};
+
+template <typename T> struct FwhtReg { using R = T; };
+template <> struct FwhtReg<int32_t> { using R = uint32_t; };   // wrap-around arithmetic
+template <> struct FwhtReg<uint16_t> { using R = uint32_t; };  // exact mod 2^16 after truncation
+
+template <typename T, int EB>
+__global__ void __launch_bounds__(512) fwht_sweep_kernel(const FwhtArgs a) {
+  using R = typename FwhtReg<T>::R;
+  constexpr int E = 1 << EB;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  T* data = reinterpret_cast<T*>(a.data);
+  const uint32_t tid = threadIdx.x;
+  const int P = a.g.P, q0 = a.g.q0;
+  const uint64_t base = block_base(blockIdx.x, a.g.tb, P, q0);
+  R v[E];
+  int w = a.g.tb - EB;
+#pragma unroll
+  for (int k = 0; k < E; ++k) v[k] = (R)data[base + tile_off(tmap<EB>(tid, k, w), P, q0)];
+  for (int ci = 0; ci < a.g.nchunks; ++ci) {
+    const Chunk ch = a.g.chunk[ci];
+    if (ch.w != w) {
+#pragma unroll
+      for (int k = 0; k < E; ++k) lds[swz<sizeof(T)>(tmap<EB>(tid, k, w))] = (T)v[k];
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < E; ++k) v[k] = (R)lds[swz<sizeof(T)>(tmap<EB>(tid, k, ch.w))];
+      __syncthreads();
+      w = ch.w;
+    }
+#pragma unroll
+    for (int j = 0; j < EB; ++j) {
+      if (j >= ch.jlo && j < ch.jhi) {
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+          if (!(k & (1 << j))) {
+            const R u = v[k], x = v[k | (1 << j)];
+            v[k] = u + x;
+            v[k | (1 << j)] = u - x;
+          }
+        }
+      }
+    }
+  }
+  if (w != a.g.w_store) {
+#pragma unroll
+    for (int k = 0; k < E; ++k) lds[swz<sizeof(T)>(tmap<EB>(tid, k, w))] = (T)v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = (R)lds[swz<sizeof(T)>(tmap<EB>(tid, k, a.g.w_store))];
+    w = a.g.w_store;
+  }
+#pragma unroll
+  for (int k = 0; k < E; ++k) data[base + tile_off(tmap<EB>(tid, k, w), P, q0)] = (T)v[k];
+}
+
+// ----------------------------------------------------------------------------
+// standalone expectation and finalisation
+// ----------------------------------------------------------------------------
+template <class S, class D>
+__global__ void __launch_bounds__(256) expectation_kernel(const void* psi, const void* diag, double offset,
+                                                          uint64_t N, double* partials) {
+  __shared__ double scratch[16];
+  double e = 0.0, q = 0.0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N; x += stride) {
+    double r, i;
+    S::load(psi, x, r, i);
+    const double pr = r * r + i * i;
+    e += pr * (D::get(diag, x) + offset);
+    q += pr;
+  }
+  block_sum2(e, q, scratch);
+  if (threadIdx.x == 0) { partials[2 * blockIdx.x] = e; partials[2 * blockIdx.x + 1] = q; }
+}
+
+__global__ void __launch_bounds__(256) finalize_kernel(const double* partials, uint64_t count, double* out) {
+  __shared__ double scratch[16];
+  double e = 0.0, q = 0.0;
+  for (uint64_t i = threadIdx.x; i < count; i += blockDim.x) { e += partials[2 * i]; q += partials[2 * i + 1]; }
+  block_sum2(e, q, scratch);
+  if (threadIdx.x == 0) { out[0] = e; out[1] = q; }
+}
+
+template <class S>
+__global__ void __launch_bounds__(256) fill_state_kernel(void* psi, uint64_t N, double amp) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N; x += stride) S::store(psi, x, amp, 0.0);
+}
+
+// ----------------------------------------------------------------------------
+// precompute helpers
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) zero_kernel(T* p, uint64_t N) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N; x += stride) p[x] = (T)0;
+}
+
+template <typename T>
+struct ScatterArgs {
+  T* data;
+  int count;
+  uint64_t mask[kScatterChunk];
+  T val[kScatterChunk];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) scatter_kernel(const ScatterArgs<T> a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < a.count) a.data[a.mask[i]] = a.val[i];
+}
+
+// per-block (min, max, OR of low bits) of an int32 vector
+__global__ void __launch_bounds__(256) int_stats_kernel(const int32_t* p, uint64_t N, int32_t lowmask, int64_t* partials) {
+  __shared__ int64_t smin[256], smax[256], sor[256];
+  int64_t mn = INT64_MAX, mx = INT64_MIN, orr = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N; x += stride) {
+    const int64_t v = p[x];
+    mn = v < mn ? v : mn;
+    mx = v > mx ? v : mx;
+    orr |= (v & lowmask);
+  }
+  smin[threadIdx.x] = mn; smax[threadIdx.x] = mx; sor[threadIdx.x] = orr;
+  __syncthreads();
+  for (uint32_t s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      smin[threadIdx.x] = smin[threadIdx.x + s] < smin[threadIdx.x] ? smin[threadIdx.x + s] : smin[threadIdx.x];
+      smax[threadIdx.x] = smax[threadIdx.x + s] > smax[threadIdx.x] ? smax[threadIdx.x + s] : smax[threadIdx.x];
+      sor[threadIdx.x] |= sor[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partials[3 * blockIdx.x] = smin[0];
+    partials[3 * blockIdx.x + 1] = smax[0];
+    partials[3 * blockIdx.x + 2] = sor[0];
+  }
+}
+
+__global__ void __launch_bounds__(64) int_stats_finalize(const int64_t* partials, int count, int64_t* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int64_t mn = INT64_MAX, mx = INT64_MIN, orr = 0;
+    for (int i = 0; i < count; ++i) {
+      mn = partials[3 * i] < mn ? partials[3 * i] : mn;
+      mx = partials[3 * i + 1] > mx ? partials[3 * i + 1] : mx;
+      orr |= partials[3 * i + 2];
+    }
+    out[0] = mn; out[1] = mx; out[2] = orr;
+  }
+}
+
+// dst[x] = (src[x] >> k) - sub   (src holds 2^k * c, exactly divisible)
+template <typename TD>
+__global__ void __launch_bounds__(256) narrow_kernel(const int32_t* src, TD* dst, uint64_t N, int k, int64_t sub) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N; x += stride)
+    dst[x] = (TD)((int64_t)(src[x] >> k) - sub);
+}
+
+}  // namespace qk

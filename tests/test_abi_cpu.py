@@ -1,0 +1,209 @@
+"""CPU checks of the C ABI: exports, argument validation, and the sweep plans.
+
+No compute calls are made here.  The plan checks emulate, on the CPU, the index
+arithmetic every sweep kernel uses (tile element -> global element, register
+window mapping, LDS swizzle), so a plan that would read or write out of bounds,
+touch an element twice, or skip or repeat a qubit fails here before any GPU run.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2309_04841_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qaoa.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qaoa_\w+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    names = _declared()
+    assert set(names) == set(_lib.EXPORTS)
+    raw = ctypes.CDLL(_lib.LIB_PATH)
+    for name in names:
+        assert hasattr(raw, name), name
+
+
+def test_version_and_last_error():
+    assert re.match(r"\d+\.\d+\.\d+", _lib.version())
+    size = ctypes.c_size_t(0)
+    assert _lib.lib.qaoa_workspace_bytes(_lib.QAOA_OP_EVOLVE, 0, 1, 1, ctypes.byref(size)) == _lib.QAOA_ERR_INVALID
+    assert b"out of range" in _lib.lib.qaoa_last_error()
+
+
+def test_workspace_bytes():
+    assert _lib.workspace_bytes(_lib.QAOA_OP_EVOLVE, 26, _lib.QAOA_C128) == 16 * (1 << 14)
+    assert _lib.workspace_bytes(_lib.QAOA_OP_PRECOMPUTE, 20, diag_dtype=_lib.QAOA_DIAG_F64) == 0
+    assert _lib.workspace_bytes(_lib.QAOA_OP_PRECOMPUTE, 20, diag_dtype=_lib.QAOA_DIAG_U16) >= 4 << 20
+    with pytest.raises(_lib.QaoaError):
+        _lib.workspace_bytes(9, 10)
+
+
+# ---------------------------------------------------------------------------
+# validation: every case fails before anything is enqueued
+# ---------------------------------------------------------------------------
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: each call fails validation first
+
+
+def _evolve(n=10, p=1, gamma=(0.1,), beta=(0.2,), diag=FAKE, ddt=1, off=0.0, dbytes=None,
+            state=FAKE, sdt=1, sbytes=None, init=1, out=None, work=None, wbytes=0):
+    N = 1 << max(n, 0) if 0 <= n < 40 else 0
+    dbytes = 4 * N if dbytes is None else dbytes
+    sbytes = 16 * N if sbytes is None else sbytes
+    g = (ctypes.c_double * max(1, len(gamma)))(*gamma) if gamma is not None else None
+    b = (ctypes.c_double * max(1, len(beta)))(*beta) if beta is not None else None
+    return _lib.lib.qaoa_evolve(n, p, g, b, diag, ddt, off, dbytes, state, sdt, sbytes, init, out, work, wbytes, None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=0), _lib.QAOA_ERR_INVALID),
+    (dict(n=35), _lib.QAOA_ERR_INVALID),
+    (dict(p=-1), _lib.QAOA_ERR_INVALID),
+    (dict(sdt=7), _lib.QAOA_ERR_INVALID),
+    (dict(ddt=7), _lib.QAOA_ERR_INVALID),
+    (dict(state=None), _lib.QAOA_ERR_INVALID),
+    (dict(diag=None), _lib.QAOA_ERR_INVALID),
+    (dict(gamma=None), _lib.QAOA_ERR_INVALID),
+    (dict(gamma=(float("nan"),)), _lib.QAOA_ERR_INVALID),
+    (dict(beta=(float("inf"),)), _lib.QAOA_ERR_INVALID),
+    (dict(off=0.5), _lib.QAOA_ERR_INVALID),
+    (dict(init=2), _lib.QAOA_ERR_INVALID),
+    (dict(sbytes=100), _lib.QAOA_ERR_NOMEM),
+    (dict(dbytes=100), _lib.QAOA_ERR_NOMEM),
+    (dict(out=FAKE), _lib.QAOA_ERR_NOMEM),
+    (dict(out=FAKE, work=FAKE, wbytes=8), _lib.QAOA_ERR_NOMEM),
+])
+def test_evolve_rejects(kw, code):
+    assert _evolve(**kw) == code
+    assert _lib.lib.qaoa_last_error() != b""
+
+
+def _precompute(n=6, w=(1.0,), ptr=(0, 2), idx=(0, 1), ddt=1, diag=FAKE, dbytes=None, work=None, wbytes=0,
+                offset=True):
+    N = 1 << n if 0 < n < 40 else 0
+    dbytes = 8 * N if dbytes is None else dbytes
+    wa = (ctypes.c_double * max(1, len(w)))(*w)
+    pa = (ctypes.c_int64 * len(ptr))(*ptr)
+    ia = (ctypes.c_int32 * max(1, len(idx)))(*idx) if idx is not None else None
+    off = ctypes.c_double(0) if offset else None
+    return _lib.lib.qaoa_precompute_diag(n, len(w), wa, pa, ia, ddt, diag, dbytes,
+                                         ctypes.byref(off) if offset else None, work, wbytes, None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=0), _lib.QAOA_ERR_INVALID),
+    (dict(idx=(0, 6)), _lib.QAOA_ERR_INVALID),
+    (dict(idx=(-1, 2)), _lib.QAOA_ERR_INVALID),
+    (dict(ptr=(1, 2)), _lib.QAOA_ERR_INVALID),
+    (dict(w=(1.0, 2.0), ptr=(0, 2, 1)), _lib.QAOA_ERR_INVALID),
+    (dict(w=(float("nan"),)), _lib.QAOA_ERR_INVALID),
+    (dict(ddt=9), _lib.QAOA_ERR_INVALID),
+    (dict(diag=None), _lib.QAOA_ERR_INVALID),
+    (dict(offset=False), _lib.QAOA_ERR_INVALID),
+    (dict(dbytes=10), _lib.QAOA_ERR_NOMEM),
+    (dict(w=(0.3,)), _lib.QAOA_ERR_RANGE),                  # not dyadic: not an integer vector
+    (dict(w=(2.0 ** 31,)), _lib.QAOA_ERR_RANGE),            # beyond int32
+    (dict(w=(1.0,), ddt=2, wbytes=0, idx=(0, 1)), None),   # placeholder, replaced below
+])
+def test_precompute_rejects(kw, code):
+    if code is None:
+        # U16 needing the int32 scratch (half-integer weight) without a workspace
+        assert _precompute(w=(0.5,), ddt=2) == _lib.QAOA_ERR_NOMEM
+        return
+    assert _precompute(**kw) == code
+
+
+def test_grad_validates_then_unsupported():
+    N = 1 << 8
+    g = (ctypes.c_double * 1)(0.1)
+    assert _lib.lib.qaoa_grad(8, 1, g, g, FAKE, 1, 0.0, 4 * N, FAKE, None, 1, 16 * N, FAKE, None, 0, None) \
+        == _lib.QAOA_ERR_INVALID
+    assert _lib.lib.qaoa_grad(8, 1, g, g, FAKE, 1, 0.0, 4 * N, FAKE, FAKE, 1, 16 * N, FAKE, None, 0, None) \
+        == _lib.QAOA_ERR_UNSUPPORTED
+
+
+# ---------------------------------------------------------------------------
+# sweep plans: emulate the kernels' index arithmetic
+# ---------------------------------------------------------------------------
+def tmap(tid, k, w, eb):
+    return (tid & ((1 << w) - 1)) | (k << w) | ((tid >> w) << (w + eb))
+
+
+def tile_off(t, P, q0):
+    return (t & ((1 << P) - 1)) | ((t >> P) << q0)
+
+
+def block_base(b, tb, P, q0):
+    nlow = q0 - P
+    return ((b & ((1 << nlow) - 1)) << P) | ((b >> nlow) << (q0 + tb - P))
+
+
+def swz(t, elem_bytes):
+    return t ^ ((t >> 4) & 15) if elem_bytes >= 16 else t ^ ((t >> 5) & 31)
+
+
+def _check_plan(n, plan, elem_bytes, emulate):
+    eb = plan["eb"]
+    seen = []
+    for si, s in enumerate(plan["sweeps"]):
+        tb, P, q0 = s["tb"], s["P"], s["q0"]
+        assert 1 <= tb <= n and 0 <= P <= tb
+        assert tb - eb <= 9, "more than 512 threads"
+        assert (1 << tb) * elem_bytes <= 65536, "tile exceeds 64 KiB of LDS"
+        if si == 0:
+            assert P == 0 and q0 == 0
+        assert q0 >= P and q0 + (tb - P) <= n
+        assert 0 <= s["w_store"] <= tb - eb
+        assert s["chunks"][0][0] == tb - eb, "first window must be the load mapping"
+        for (w, jlo, jhi) in s["chunks"]:
+            assert 0 <= w <= tb - eb and 0 <= jlo < jhi <= eb
+            for j in range(jlo, jhi):
+                t = w + j
+                assert t >= P, "butterfly on a passenger bit"
+                seen.append(q0 + (t - P))
+        if emulate:
+            nthreads = 1 << (tb - eb)
+            tid = np.arange(nthreads)[:, None]
+            k = np.arange(1 << eb)[None, :]
+            windows = {c[0] for c in s["chunks"]} | {s["w_store"]}
+            for w in windows:
+                t = tmap(tid, k, w, eb).ravel()
+                assert np.array_equal(np.sort(t), np.arange(1 << tb))
+                pos = swz(t, elem_bytes)
+                assert np.array_equal(np.sort(pos), np.arange(1 << tb))
+                off = tile_off(t, P, q0)
+                blocks = np.arange(1 << (n - tb))[:, None]
+                g = (block_base(blocks, tb, P, q0) | off[None, :]).ravel()
+                assert g.min() >= 0 and g.max() < (1 << n)
+                assert np.array_equal(np.sort(g), np.arange(1 << n)), "sweep does not cover every element once"
+    assert sorted(seen) == list(range(n)), "every qubit must be butterflied exactly once per layer"
+
+
+@pytest.mark.parametrize("sdt,eb", [(_lib.QAOA_C128, 16), (_lib.QAOA_C64, 8)])
+def test_state_plans(sdt, eb):
+    for n in range(1, _lib.QAOA_MAX_QUBITS + 1):
+        plan = _lib.plan_describe(n, sdt)
+        _check_plan(n, plan, eb, emulate=n <= 17)
+        if plan["single"]:
+            assert len(plan["sweeps"]) == 1
+
+
+@pytest.mark.parametrize("elem", [2, 4, 8])
+def test_transform_plans(elem):
+    for n in range(1, _lib.QAOA_MAX_QUBITS + 1):
+        _check_plan(n, _lib.plan_describe(n, -1, elem), elem, emulate=n <= 16)
+
+
+def test_headline_plans_sweep_counts():
+    # LABS n=26 complex128 and n=31 complex64 both take three HBM sweeps per layer
+    assert len(_lib.plan_describe(26, _lib.QAOA_C128)["sweeps"]) == 3
+    assert len(_lib.plan_describe(31, _lib.QAOA_C64)["sweeps"]) == 3
+    assert _lib.plan_describe(12, _lib.QAOA_C128)["single"]

