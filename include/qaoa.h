@@ -125,11 +125,16 @@ int qaoa_precompute_diag(int n, int64_t num_terms, const double *w, const int64_
  *   d_out       device, nullable: receives d_out[0] = E = sum |psi|^2 c and
  *               d_out[1] = sum |psi|^2 of the final state (FP64, no renormalisation)
  *   d_work      device workspace, >= qaoa_workspace_bytes(QAOA_OP_EVOLVE, ...) bytes
- *               when d_out != NULL (may be NULL otherwise)
+ *               (may be NULL only when p == 0 and d_out == NULL)
  *
- * Phase angles are formed as gamma_l * c[x] in double precision for both state
- * dtypes; complex64 states are updated in double precision and rounded to float
- * when stored.  Results are deterministic (fixed reduction order).
+ * Phase factors: for F64 cost vectors exp(-i gamma_l c) is evaluated from the
+ * double-precision angle gamma_l * c[x].  For integer cost vectors (I32 values in
+ * [-2^15, 2^15), all U16 values) it is the product of two table entries
+ * exp(-i gamma_l (256 m + base)) * exp(-i gamma_l j) with c = 256 m + j + base,
+ * each evaluated in double precision (agreeing with the direct evaluation to a
+ * few units in the last place of the angle); other I32 values use the direct
+ * evaluation.  complex64 states are updated in double precision and rounded to
+ * float when stored.  Results are deterministic (fixed reduction order).
  */
 int qaoa_evolve(int n, int p, const double *gamma, const double *beta,
                 const void *d_diag, int diag_dtype, double diag_offset, size_t diag_bytes,

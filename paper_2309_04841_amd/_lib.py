@@ -182,7 +182,7 @@ def qaoa_evolve(n: int, gamma, beta, diag: torch.Tensor, state: torch.Tensor, in
     if len(beta) != p:
         raise ValueError("gamma and beta differ in length")
     sdt, ddt = state_dtype_code(state), diag_dtype_code(diag)
-    if out is not None and work is None:
+    if work is None and (p > 0 or out is not None):
         work = alloc_workspace(QAOA_OP_EVOLVE, n, sdt, ddt, state.device)
     check(lib.qaoa_evolve(n, p, _f64(gamma), _f64(beta), _dev_ptr(diag), ddt, float(diag_offset), _nbytes(diag),
                           _dev_ptr(state), sdt, _nbytes(state), 1 if init else 0, _dev_ptr(out),

@@ -65,21 +65,71 @@ struct C64 {  // complex64 storage, FP64 arithmetic in registers
   }
 };
 
+// Cost-vector policies.  `get` returns the stored value as a double (the
+// cost is get() + offset).  For integer storage, `tab_index` maps the stored
+// value to an index u in [0, 2^16) of the per-layer phase table, or returns a
+// negative value when the table does not cover it (then sincos is used).
 struct DI32 {
+  static constexpr bool kTable = true;
   __device__ static __forceinline__ double get(const void* p, uint64_t x) {
     return (double)reinterpret_cast<const int32_t*>(p)[x];
   }
+  __device__ static __forceinline__ int32_t raw(const void* p, uint64_t x) {
+    return reinterpret_cast<const int32_t*>(p)[x];
+  }
+  // table covers stored values in [-2^15, 2^15)
+  __device__ static __forceinline__ int32_t tab_index(int32_t v) {
+    const uint32_t u = (uint32_t)v + 32768u;
+    return u < 65536u ? (int32_t)u : -1;
+  }
+  static constexpr double kTableBase = -32768.0;
 };
 struct DU16 {
+  static constexpr bool kTable = true;
   __device__ static __forceinline__ double get(const void* p, uint64_t x) {
     return (double)reinterpret_cast<const uint16_t*>(p)[x];
   }
+  __device__ static __forceinline__ int32_t raw(const void* p, uint64_t x) {
+    return (int32_t)reinterpret_cast<const uint16_t*>(p)[x];
+  }
+  __device__ static __forceinline__ int32_t tab_index(int32_t v) { return v; }
+  static constexpr double kTableBase = 0.0;
 };
 struct DF64 {
+  static constexpr bool kTable = false;
   __device__ static __forceinline__ double get(const void* p, uint64_t x) {
     return reinterpret_cast<const double*>(p)[x];
   }
+  __device__ static __forceinline__ int32_t raw(const void*, uint64_t) { return 0; }
+  __device__ static __forceinline__ int32_t tab_index(int32_t) { return -1; }
+  static constexpr double kTableBase = 0.0;
 };
+
+// Phase tables for integer cost vectors.  With u = stored - base in [0, 2^16)
+// the cost is c = u + base + offset, and
+//   exp(-i g c) = HI[u >> 8] * LO[u & 255],
+//   HI[m] = exp(-i g (256 m + base + offset)),  LO[j] = exp(-i g j),
+// each entry from one sincos of an exactly representable integer times g.
+constexpr int kTabEntries = 512;  // HI (256) then LO (256), double2 (cos, -sin)
+
+struct PhaseTableArgs {
+  double2* out;      // [nlayers][512]
+  double base;       // table base + cost offset
+  int nlayers;
+  double gamma[32];
+};
+
+__global__ void __launch_bounds__(256) phase_table_kernel(const PhaseTableArgs a) {
+  const int l = blockIdx.x;
+  if (l >= a.nlayers) return;
+  const double g = a.gamma[l];
+  for (int e = threadIdx.x; e < kTabEntries; e += blockDim.x) {
+    const double v = e < 256 ? 256.0 * (double)e + a.base : (double)(e - 256);
+    double sn, cs;
+    sincos(g * v, &sn, &cs);
+    a.out[(size_t)l * kTabEntries + e] = make_double2(cs, -sn);
+  }
+}
 
 // ----------------------------------------------------------------------------
 // reductions
@@ -127,6 +177,7 @@ __device__ __forceinline__ void block_sum2(double& x, double& y, double* scratch
 struct SweepArgs {
   void* psi;
   const void* diag;
+  const double2* ptab; // phase tables of this launch's layers (integer cost vectors)
   double* partials;   // 2 doubles per block (E, norm) when F_EXPV
   double diag_offset;
   double amp0;        // 2^{-n/2} for F_INIT
@@ -178,19 +229,36 @@ __global__ void __launch_bounds__(512) qaoa_sweep_kernel(const SweepArgs a) {
     for (int k = 0; k < E; ++k) S::load(a.psi, base + tile_off(tmap<EB>(tid, k, w), P, q0), vr[k], vi[k]);
   }
 
+  const uint32_t tile_bytes = (1u << a.g.tb) * S::kBytes;
+  double2* tab = reinterpret_cast<double2*>(smem_raw + tile_bytes);
   for (int l = 0; l < a.nlayers; ++l) {
     if (a.flags & F_PHASE) {
       const double g = a.gamma[l];
+      if constexpr (D::kTable) {
+        // stage this layer's tables in LDS (the previous layer's reads of the
+        // tables finished before the exchanges that followed them)
+        if (l > 0) __syncthreads();
+        for (uint32_t e = tid; e < (uint32_t)kTabEntries; e += blockDim.x) tab[e] = a.ptab[(size_t)l * kTabEntries + e];
+        __syncthreads();
+      }
 #pragma unroll
       for (int k = 0; k < E; ++k) {
         const uint64_t x = base + tile_off(tmap<EB>(tid, k, w), P, q0);
-        const double c = D::get(a.diag, x) + a.diag_offset;
-        double sn, cs;
-        sincos(g * c, &sn, &cs);
-        // multiply by exp(-i g c) = cs - i sn
+        double cs, sn;  // exp(-i g c) = cs + i sn
+        const int32_t u = D::tab_index(D::raw(a.diag, x));
+        if (D::kTable && u >= 0) {
+          const double2 h = tab[u >> 8], lo = tab[256 + (u & 255)];
+          cs = fma(h.x, lo.x, -h.y * lo.y);
+          sn = fma(h.x, lo.y, h.y * lo.x);
+        } else {
+          const double c = D::get(a.diag, x) + a.diag_offset;
+          double s0;
+          sincos(g * c, &s0, &cs);
+          sn = -s0;
+        }
         const double r = vr[k], im = vi[k];
-        vr[k] = fma(cs, r, sn * im);
-        vi[k] = fma(cs, im, -sn * r);
+        vr[k] = fma(cs, r, -sn * im);
+        vi[k] = fma(cs, im, sn * r);
       }
     }
     const double ca = a.ca[l], sb = a.sb[l];

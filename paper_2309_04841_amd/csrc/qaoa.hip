@@ -129,8 +129,11 @@ uint64_t plan_blocks(int n, const qk::TileGeom& g) { return (uint64_t)1 << (n - 
 template <class S, class D, int EB>
 void launch_sweep_t(const qk::SweepArgs& a, uint64_t blocks, hipStream_t st) {
   const uint32_t threads = 1u << (a.g.tb - EB);
-  // tile buffer; also the reduction scratch (16 doubles, or 2 per thread for a partial wave)
-  const size_t lds = std::max<size_t>(((size_t)1 << a.g.tb) * S::kBytes, std::max<size_t>(16, 2 * threads) * sizeof(double));
+  // tile buffer + phase tables; also the reduction scratch (16 doubles, or 2 per
+  // thread for a partial wave), which is used after the tables are done with
+  const size_t tile = ((size_t)1 << a.g.tb) * S::kBytes;
+  const size_t tab = (D::kTable && (a.flags & qk::F_PHASE)) ? qk::kTabEntries * sizeof(double2) : 0;
+  const size_t lds = std::max<size_t>(tile + tab, std::max<size_t>(16, 2 * threads) * sizeof(double));
   hipLaunchKernelGGL((qk::qaoa_sweep_kernel<S, D, EB>), dim3((uint32_t)blocks), dim3(threads), lds, st, a);
 }
 
@@ -255,6 +258,32 @@ int int_stats(int n, const int32_t* data, int32_t lowmask, void* work, int64_t o
 
 constexpr size_t kStatWork = (3 * kStatBlocks + 4) * sizeof(int64_t);
 
+// Evolve workspace: [per-block (E, norm) partials][phase tables of up to
+// kMaxLayersPerLaunch layers].
+size_t partials_bytes(int n, int state_dtype) {
+  const Plan pl = make_plan(n, state_elem_bytes(state_dtype));
+  const uint64_t last = plan_blocks(n, pl.sweeps.back());
+  return 2 * sizeof(double) * std::max<uint64_t>(last, kExpectBlocks);
+}
+constexpr size_t kTableBytes = (size_t)qk::kMaxLayersPerLaunch * qk::kTabEntries * sizeof(double2);
+size_t evolve_work_bytes(int n, int state_dtype) { return partials_bytes(n, state_dtype) + kTableBytes; }
+
+// Phase tables for layers [l0, l0 + nl) into `tab` (integer cost vectors only).
+int enqueue_phase_tables(double2* tab, const double* gamma, int l0, int nl, double base, hipStream_t st) {
+  qk::PhaseTableArgs t{};
+  t.out = tab;
+  t.base = base;
+  t.nlayers = nl;
+  for (int i = 0; i < nl; ++i) t.gamma[i] = gamma[l0 + i];
+  hipLaunchKernelGGL(qk::phase_table_kernel, dim3(nl), dim3(256), 0, st, t);
+  LAUNCH_CHECK("phase_table_kernel");
+  return QAOA_OK;
+}
+
+double table_base(int diag_dtype, double diag_offset) {
+  return (diag_dtype == QAOA_DIAG_I32 ? qk::DI32::kTableBase : qk::DU16::kTableBase) + diag_offset;
+}
+
 }  // namespace
 
 extern "C" {
@@ -276,9 +305,7 @@ int qaoa_workspace_bytes(int op, int n, int state_dtype, int diag_dtype, size_t*
     case QAOA_OP_EXPECTATION:
     case QAOA_OP_GRAD: {
       if (!valid_state_dtype(state_dtype)) return fail(QAOA_ERR_INVALID, "bad state dtype %d", state_dtype);
-      const Plan pl = make_plan(n, state_elem_bytes(state_dtype));
-      const uint64_t last = plan_blocks(n, pl.sweeps.back());
-      *bytes = 2 * sizeof(double) * std::max<uint64_t>(last, kExpectBlocks);
+      *bytes = evolve_work_bytes(n, state_dtype);
       return QAOA_OK;
     }
     default:
@@ -475,9 +502,8 @@ int qaoa_evolve(int n, int p, const double* gamma, const double* beta, const voi
   rc = validate_angles(p, gamma, beta);
   if (rc) return rc;
   if (init != 0 && init != 1) return fail(QAOA_ERR_INVALID, "init must be 0 or 1");
-  size_t need = 0;
-  if (d_out) {
-    qaoa_workspace_bytes(QAOA_OP_EVOLVE, n, state_dtype, diag_dtype, &need);
+  if (p > 0 || d_out) {
+    const size_t need = evolve_work_bytes(n, state_dtype);
     if (!d_work || work_bytes < need) return fail(QAOA_ERR_NOMEM, "workspace too small: need %zu bytes", need);
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -503,6 +529,10 @@ int qaoa_evolve(int n, int p, const double* gamma, const double* beta, const voi
   a.diag_offset = diag_offset;
   a.amp0 = amp0;
   double* partials = reinterpret_cast<double*>(d_work);
+  double2* tab = reinterpret_cast<double2*>(reinterpret_cast<char*>(d_work) + partials_bytes(n, state_dtype));
+  const bool use_tab = diag_dtype != QAOA_DIAG_F64;
+  const double tbase = use_tab ? table_base(diag_dtype, diag_offset) : 0.0;
+  a.ptab = tab;
 
   if (pl.single) {
     // whole state in one tile: up to kMaxLayersPerLaunch layers per launch
@@ -510,6 +540,10 @@ int qaoa_evolve(int n, int p, const double* gamma, const double* beta, const voi
     for (int l0 = 0; l0 < p; l0 += qk::kMaxLayersPerLaunch) {
       const int nl = std::min(qk::kMaxLayersPerLaunch, p - l0);
       const bool last = (l0 + nl == p);
+      if (use_tab) {
+        const int rc2 = enqueue_phase_tables(tab, gamma, l0, nl, tbase, st);
+        if (rc2) return rc2;
+      }
       a.flags = qk::F_PHASE | ((l0 == 0 && init) ? qk::F_INIT : 0) | ((last && d_out) ? qk::F_EXPV : 0);
       a.nlayers = nl;
       for (int i = 0; i < nl; ++i) {
@@ -526,6 +560,11 @@ int qaoa_evolve(int n, int p, const double* gamma, const double* beta, const voi
 
   const size_t nsw = pl.sweeps.size();
   for (int l = 0; l < p; ++l) {
+    if (use_tab && l % qk::kMaxLayersPerLaunch == 0) {
+      const int rc2 = enqueue_phase_tables(tab, gamma, l, std::min(qk::kMaxLayersPerLaunch, p - l), tbase, st);
+      if (rc2) return rc2;
+    }
+    a.ptab = tab + (size_t)(l % qk::kMaxLayersPerLaunch) * qk::kTabEntries;
     for (size_t s = 0; s < nsw; ++s) {
       a.g = pl.sweeps[s];
       a.nlayers = 1;

@@ -59,7 +59,7 @@ class Simulator:
         else:
             psi = torch.as_tensor(initial_state).to(device=self.device, dtype=self.state_dtype).contiguous().clone()
             init = False
-        _lib.qaoa_evolve(self.n, gamma, beta, self.diag, psi, init=init, diag_offset=self.offset)
+        _lib.qaoa_evolve(self.n, gamma, beta, self.diag, psi, init=init, diag_offset=self.offset, work=self._work)
         return psi
 
     # -- outputs -----------------------------------------------------------

@@ -40,7 +40,8 @@ def test_version_and_last_error():
 
 
 def test_workspace_bytes():
-    assert _lib.workspace_bytes(_lib.QAOA_OP_EVOLVE, 26, _lib.QAOA_C128) == 16 * (1 << 14)
+    # per-block (E, norm) partials of the last sweep + phase tables of 32 layers
+    assert _lib.workspace_bytes(_lib.QAOA_OP_EVOLVE, 26, _lib.QAOA_C128) == 16 * (1 << 14) + 32 * 512 * 16
     assert _lib.workspace_bytes(_lib.QAOA_OP_PRECOMPUTE, 20, diag_dtype=_lib.QAOA_DIAG_F64) == 0
     assert _lib.workspace_bytes(_lib.QAOA_OP_PRECOMPUTE, 20, diag_dtype=_lib.QAOA_DIAG_U16) >= 4 << 20
     with pytest.raises(_lib.QaoaError):
