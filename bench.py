@@ -92,7 +92,20 @@ def main(argv=None):
     ap.add_argument("--config", choices=sorted(CONFIGS), default="labs26")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (torch), the reference for HBM counter scaling")
     args = ap.parse_args(argv)
+
+    if args.copy_calibration:
+        import torch
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_read": nbytes, "bytes_written": nbytes, "dispatches": 3}}))
+        return 0
 
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); the hot path is "

@@ -152,6 +152,35 @@ int qaoa_expectation(int n, const void *d_state, int state_dtype, size_t state_b
                      double *d_out, void *d_work, size_t work_bytes, void *stream);
 
 /*
+ * qaoa_evolve_batch -- `batch` independent QAOA evaluations against one cost
+ * vector (the repeated objective evaluations of an outer optimiser, Section 2
+ * and Fig. 1): state s evolves through Algorithm 3 with its own angles.
+ *
+ *   d_gamma, d_beta  device, row-major [batch][p] doubles; read when the
+ *               enqueued work runs (not at call time), so a caller may capture
+ *               the call in a HIP graph and replay it after writing new angles
+ *               into the same buffers.  Non-finite angles give non-finite results.
+ *   d_states    device, [batch][2^n] states of state_dtype (states_bytes);
+ *               init = 1 starts every state from |+>^n, init = 0 from its contents
+ *   d_out       device, nullable, [batch][2] doubles: (E, sum |psi|^2) per state
+ *   sets_per_pass  states advanced together through all layers before the next
+ *               group starts (0 = all).  Smaller groups keep their states resident
+ *               in the memory-side cache; the result does not depend on it.
+ *   d_work      device workspace of qaoa_batch_workspace_bytes(n, p, batch, ...)
+ *
+ * The same kernels and reduction order as qaoa_evolve are used, so each state's
+ * result is bitwise equal to a qaoa_evolve call with its angles.  Enqueues only
+ * kernels (no memset, copy or synchronisation), so it can be graph-captured.
+ */
+int qaoa_evolve_batch(int n, int p, int batch, const double *d_gamma, const double *d_beta,
+                      const void *d_diag, int diag_dtype, double diag_offset, size_t diag_bytes,
+                      void *d_states, int state_dtype, size_t states_bytes, int init,
+                      double *d_out, int sets_per_pass, void *d_work, size_t work_bytes, void *stream);
+
+/* Workspace bytes qaoa_evolve_batch needs for these sizes and dtypes. */
+int qaoa_batch_workspace_bytes(int n, int p, int batch, int state_dtype, int diag_dtype, size_t *bytes);
+
+/*
  * qaoa_grad -- E and its gradient with respect to gamma[0..p) and beta[0..p)
  * by reverse-mode evolution (adjoint method).  d_out receives 1 + 2p doubles:
  * E, dE/dgamma[0..p), dE/dbeta[0..p).  d_state and d_adj are two caller-owned

@@ -21,7 +21,8 @@ QAOA_OP_PRECOMPUTE, QAOA_OP_EVOLVE, QAOA_OP_EXPECTATION, QAOA_OP_GRAD = range(4)
 QAOA_MAX_QUBITS = 34
 
 EXPORTS = ("qaoa_version", "qaoa_last_error", "qaoa_workspace_bytes", "qaoa_precompute_diag",
-           "qaoa_evolve", "qaoa_expectation", "qaoa_grad", "qaoa_plan_describe")
+           "qaoa_evolve", "qaoa_expectation", "qaoa_grad", "qaoa_plan_describe", "qaoa_evolve_batch",
+           "qaoa_batch_workspace_bytes")
 
 _STATUS_NAMES = {0: "QAOA_OK", 1: "QAOA_ERR_INVALID", 2: "QAOA_ERR_RANGE", 3: "QAOA_ERR_NOMEM",
                  4: "QAOA_ERR_DEVICE", 5: "QAOA_ERR_UNSUPPORTED"}
@@ -55,6 +56,10 @@ def _load() -> ctypes.CDLL:
     lib.qaoa_grad.argtypes = [I, I, P, P, P, I, D, SZ, P, P, I, SZ, P, P, SZ, P]
     lib.qaoa_plan_describe.restype = I
     lib.qaoa_plan_describe.argtypes = [I, I, I, P, I]
+    lib.qaoa_evolve_batch.restype = I
+    lib.qaoa_evolve_batch.argtypes = [I, I, I, P, P, P, I, D, SZ, P, I, SZ, I, P, I, P, SZ, P]
+    lib.qaoa_batch_workspace_bytes.restype = I
+    lib.qaoa_batch_workspace_bytes.argtypes = [I, I, I, I, I, ctypes.POINTER(SZ)]
     return lib
 
 
@@ -215,3 +220,32 @@ def qaoa_grad(n: int, gamma, beta, diag: torch.Tensor, state: torch.Tensor, adj:
                         _dev_ptr(state), _dev_ptr(adj), sdt, _nbytes(state), _dev_ptr(out), _dev_ptr(work),
                         _nbytes(work), _stream(state.device)))
     return out
+
+
+def batch_workspace_bytes(n: int, p: int, batch: int, state_dtype: int, diag_dtype: int) -> int:
+    out = ctypes.c_size_t(0)
+    check(lib.qaoa_batch_workspace_bytes(n, p, batch, state_dtype, diag_dtype, ctypes.byref(out)))
+    return int(out.value)
+
+
+def qaoa_evolve_batch(n: int, gamma: torch.Tensor, beta: torch.Tensor, diag: torch.Tensor, states: torch.Tensor,
+                      init: bool = True, diag_offset: float = 0.0, out: torch.Tensor | None = None,
+                      sets_per_pass: int = 0, work: torch.Tensor | None = None) -> None:
+    """``batch`` evaluations: gamma, beta are float64 device tensors [batch, p];
+    states is [batch, 2^n] complex; out (float64 [batch, 2]) receives (E, norm)."""
+    if gamma.dtype != torch.float64 or beta.dtype != torch.float64 or gamma.shape != beta.shape or gamma.dim() != 2:
+        raise ValueError("gamma and beta must be float64 tensors of shape [batch, p]")
+    batch, p = gamma.shape
+    if states.dim() != 2 or states.shape[0] != batch or states.shape[1] != 1 << n:
+        raise ValueError("states must have shape [batch, 2^n]")
+    sdt, ddt = state_dtype_code(states), diag_dtype_code(diag)
+    if out is not None and (out.dtype != torch.float64 or out.numel() < 2 * batch):
+        raise ValueError("out must be float64 with 2 * batch elements")
+    if work is None:
+        work = torch.empty(max(16, batch_workspace_bytes(n, p, batch, sdt, ddt)), dtype=torch.uint8,
+                           device=states.device)
+    check(lib.qaoa_evolve_batch(n, p, batch, _dev_ptr(gamma.contiguous()) if p else None,
+                                _dev_ptr(beta.contiguous()) if p else None, _dev_ptr(diag), ddt, float(diag_offset),
+                                _nbytes(diag), _dev_ptr(states), sdt, _nbytes(states), 1 if init else 0,
+                                _dev_ptr(out), int(sets_per_pass), _dev_ptr(work), _nbytes(work),
+                                _stream(states.device)))

@@ -29,15 +29,24 @@ enum : int { F_INIT = 1, F_PHASE = 2, F_EXPV = 4 };
 // ----------------------------------------------------------------------------
 // element policies
 // ----------------------------------------------------------------------------
+// The state is streamed once per sweep: its loads and stores carry the
+// non-temporal hint so they do not displace the cost vector and tables, which
+// are re-read every layer.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec2 __attribute__((ext_vector_type(2)));
+
 struct C128 {  // complex128: (double re, double im)
   using L = double2;
   static constexpr int kBytes = 16;
+  // 64 KiB tiles + tables: two workgroups per CU by LDS, two waves per SIMD
+  static constexpr int kMinWavesPerSimd = 2;
   __device__ static __forceinline__ void load(const void* p, uint64_t x, double& r, double& i) {
-    const double2 v = reinterpret_cast<const double2*>(p)[x];
+    const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(p) + x);
     r = v.x; i = v.y;
   }
   __device__ static __forceinline__ void store(void* p, uint64_t x, double r, double i) {
-    reinterpret_cast<double2*>(p)[x] = make_double2(r, i);
+    const dvec2 v = {r, i};
+    __builtin_nontemporal_store(v, reinterpret_cast<dvec2*>(p) + x);
   }
   __device__ static __forceinline__ void lput(L* s, uint32_t pos, double r, double i) { s[pos] = make_double2(r, i); }
   __device__ static __forceinline__ void lget(const L* s, uint32_t pos, double& r, double& i) {
@@ -49,12 +58,15 @@ struct C128 {  // complex128: (double re, double im)
 struct C64 {  // complex64 storage, FP64 arithmetic in registers
   using L = float2;
   static constexpr int kBytes = 8;
+  // 512-thread tiles: four waves per SIMD keep two workgroups resident per CU
+  static constexpr int kMinWavesPerSimd = 4;
   __device__ static __forceinline__ void load(const void* p, uint64_t x, double& r, double& i) {
-    const float2 v = reinterpret_cast<const float2*>(p)[x];
+    const fvec2 v = __builtin_nontemporal_load(reinterpret_cast<const fvec2*>(p) + x);
     r = (double)v.x; i = (double)v.y;
   }
   __device__ static __forceinline__ void store(void* p, uint64_t x, double r, double i) {
-    reinterpret_cast<float2*>(p)[x] = make_float2((float)r, (float)i);
+    const fvec2 v = {(float)r, (float)i};
+    __builtin_nontemporal_store(v, reinterpret_cast<fvec2*>(p) + x);
   }
   __device__ static __forceinline__ void lput(L* s, uint32_t pos, double r, double i) {
     s[pos] = make_float2((float)r, (float)i);
@@ -71,6 +83,8 @@ struct C64 {  // complex64 storage, FP64 arithmetic in registers
 // negative value when the table does not cover it (then sincos is used).
 struct DI32 {
   static constexpr bool kTable = true;
+  __device__ static __forceinline__ int32_t load_raw(const void* p, uint64_t x) { return reinterpret_cast<const int32_t*>(p)[x]; }
+  static constexpr bool kAlwaysInTable = false;
   __device__ static __forceinline__ double get(const void* p, uint64_t x) {
     return (double)reinterpret_cast<const int32_t*>(p)[x];
   }
@@ -83,9 +97,13 @@ struct DI32 {
     return u < 65536u ? (int32_t)u : -1;
   }
   static constexpr double kTableBase = -32768.0;
+  using RawT = int32_t;
+  __device__ static __forceinline__ double value(RawT r) { return (double)r; }
 };
 struct DU16 {
   static constexpr bool kTable = true;
+  __device__ static __forceinline__ int32_t load_raw(const void* p, uint64_t x) { return (int32_t)reinterpret_cast<const uint16_t*>(p)[x]; }
+  static constexpr bool kAlwaysInTable = true;
   __device__ static __forceinline__ double get(const void* p, uint64_t x) {
     return (double)reinterpret_cast<const uint16_t*>(p)[x];
   }
@@ -94,15 +112,21 @@ struct DU16 {
   }
   __device__ static __forceinline__ int32_t tab_index(int32_t v) { return v; }
   static constexpr double kTableBase = 0.0;
+  using RawT = int32_t;
+  __device__ static __forceinline__ double value(RawT r) { return (double)r; }
 };
 struct DF64 {
   static constexpr bool kTable = false;
+  __device__ static __forceinline__ double load_raw(const void* p, uint64_t x) { return reinterpret_cast<const double*>(p)[x]; }
+  static constexpr bool kAlwaysInTable = false;
   __device__ static __forceinline__ double get(const void* p, uint64_t x) {
     return reinterpret_cast<const double*>(p)[x];
   }
   __device__ static __forceinline__ int32_t raw(const void*, uint64_t) { return 0; }
   __device__ static __forceinline__ int32_t tab_index(int32_t) { return -1; }
   static constexpr double kTableBase = 0.0;
+  using RawT = double;
+  __device__ static __forceinline__ double value(RawT r) { return r; }
 };
 
 // Phase tables for integer cost vectors.  With u = stored - base in [0, 2^16)
@@ -112,22 +136,41 @@ struct DF64 {
 // each entry from one sincos of an exactly representable integer times g.
 constexpr int kTabEntries = 512;  // HI (256) then LO (256), double2 (cos, -sin)
 
-struct PhaseTableArgs {
-  double2* out;      // [nlayers][512]
-  double base;       // table base + cost offset
-  int nlayers;
+// Per-layer parameters, computed on the device for every path so that batched
+// and single evaluations use bit-identical values: row r gets
+// pset[3r..3r+2] = (gamma, cos beta, sin beta) and, when tab != nullptr, the
+// phase tables tab[512 r ..].  Angles come from device arrays (gamma_d, beta_d)
+// or, when those are null, from the kernel arguments (at most 32 rows).
+struct PrepArgs {
+  const double* gamma_d;
+  const double* beta_d;
+  double* pset;
+  double2* tab;
+  double base;   // table base + cost offset
+  int rows;
   double gamma[32];
+  double beta[32];
 };
 
-__global__ void __launch_bounds__(256) phase_table_kernel(const PhaseTableArgs a) {
-  const int l = blockIdx.x;
-  if (l >= a.nlayers) return;
-  const double g = a.gamma[l];
-  for (int e = threadIdx.x; e < kTabEntries; e += blockDim.x) {
-    const double v = e < 256 ? 256.0 * (double)e + a.base : (double)(e - 256);
-    double sn, cs;
-    sincos(g * v, &sn, &cs);
-    a.out[(size_t)l * kTabEntries + e] = make_double2(cs, -sn);
+__global__ void __launch_bounds__(256) layer_prep_kernel(const PrepArgs a) {
+  const int r = blockIdx.x;
+  if (r >= a.rows) return;
+  const double g = a.gamma_d ? a.gamma_d[r] : a.gamma[r];
+  if (threadIdx.x == 0) {
+    const double b = a.beta_d ? a.beta_d[r] : a.beta[r];
+    double sb, cb;
+    sincos(b, &sb, &cb);
+    a.pset[3 * r] = g;
+    a.pset[3 * r + 1] = cb;
+    a.pset[3 * r + 2] = sb;
+  }
+  if (a.tab != nullptr) {
+    for (int e = threadIdx.x; e < kTabEntries; e += blockDim.x) {
+      const double v = e < 256 ? 256.0 * (double)e + a.base : (double)(e - 256);
+      double sn, cs;
+      sincos(g * v, &sn, &cs);
+      a.tab[(size_t)r * kTabEntries + e] = make_double2(cs, -sn);
+    }
   }
 }
 
@@ -177,17 +220,34 @@ __device__ __forceinline__ void block_sum2(double& x, double& y, double* scratch
 struct SweepArgs {
   void* psi;
   const void* diag;
-  const double2* ptab; // phase tables of this launch's layers (integer cost vectors)
+  const double2* ptab; // phase tables (integer cost vectors), kTabEntries per layer
   double* partials;   // 2 doubles per block (E, norm) when F_EXPV
   double diag_offset;
   double amp0;        // 2^{-n/2} for F_INIT
   int flags;
   int nlayers;        // layers applied by this launch
   TileGeom g;
-  double gamma[kMaxLayersPerLaunch];
-  double ca[kMaxLayersPerLaunch];  // cos(beta_l)
-  double sb[kMaxLayersPerLaunch];  // sin(beta_l)
+  // Parameters: layer l of state s (set = blockIdx.y for sweeps, blockIdx.x
+  // for whole-state tiles) uses row r = (set0 + s) * p_total + layer0 + l of
+  // pset (gamma, cos beta, sin beta) and of ptab.  State s starts at
+  // psi + s * set_stride_bytes and its partials at partials + s * partials_stride.
+  const double* pset;
+  int set0;
+  int p_total;
+  int layer0;
+  uint64_t set_stride_bytes;
+  uint64_t partials_stride;
 };
+
+struct LayerParams {
+  double g, ca, sb;
+  const double2* tab;
+};
+
+__device__ __forceinline__ LayerParams layer_params(const SweepArgs& a, uint32_t set, int l) {
+  const size_t r = (size_t)(a.set0 + set) * a.p_total + a.layer0 + l;
+  return LayerParams{a.pset[3 * r], a.pset[3 * r + 1], a.pset[3 * r + 2], a.ptab + r * kTabEntries};
+}
 
 // gate cos(b) I - i sin(b) X on the pair (y0, y1):
 //   y0' = a y0 - i s y1,  y1' = -i s y0 + a y1
@@ -202,23 +262,211 @@ __device__ __forceinline__ void rx_pair(double& r0, double& i0, double& r1, doub
 template <class S, int EB>
 __device__ __forceinline__ void exchange_c(double (&vr)[1 << EB], double (&vi)[1 << EB], typename S::L* lds,
                                            uint32_t tid, int wf, int wt) {
+  // linear swizzle: per-thread part once, per-register part uniform
+  const uint32_t pf = swz<S::kBytes>(thr_part<EB>(tid, wf)), pt = swz<S::kBytes>(thr_part<EB>(tid, wt));
 #pragma unroll
-  for (int k = 0; k < (1 << EB); ++k) S::lput(lds, swz<S::kBytes>(tmap<EB>(tid, k, wf)), vr[k], vi[k]);
+  for (int k = 0; k < (1 << EB); ++k) S::lput(lds, pf ^ swz<S::kBytes>((uint32_t)k << wf), vr[k], vi[k]);
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < (1 << EB); ++k) S::lget(lds, swz<S::kBytes>(tmap<EB>(tid, k, wt)), vr[k], vi[k]);
+  for (int k = 0; k < (1 << EB); ++k) S::lget(lds, pt ^ swz<S::kBytes>((uint32_t)k << wt), vr[k], vi[k]);
   __syncthreads();
 }
 
+// exp(-i g c) evaluated directly from the double-precision angle g * c.  Kept
+// out of line: it is the rare path for integer cost vectors and the only path
+// for F64 ones, and inlining sixteen copies of sincos into the unrolled tile
+// loop would cost registers and instruction cache in the common path.
+__device__ __noinline__ double2 phase_direct(double g, double c) {
+  double sn, cs;
+  sincos(g * c, &sn, &cs);
+  return make_double2(cs, -sn);
+}
+
+__device__ __forceinline__ void cmul_inplace(double& r, double& i, double fr, double fi) {
+  const double nr = fma(fr, r, -fi * i);
+  const double ni = fma(fr, i, fi * r);
+  r = nr; i = ni;
+}
+
+// Phase operator of layer l on the thread's register elements (window w).
+// Integer cost vectors use the LDS-staged tables; if any element of the
+// workgroup falls outside the table range the whole workgroup takes the
+// direct path (a workgroup-uniform branch).
 template <class S, class D, int EB>
-__global__ void __launch_bounds__(512) qaoa_sweep_kernel(const SweepArgs a) {
+__device__ __forceinline__ void apply_phase(double (&vr)[1 << EB], double (&vi)[1 << EB], const SweepArgs& a,
+                                            const LayerParams& lp, uint64_t base, uint32_t tid, int w, double2* tab) {
+  constexpr int E = 1 << EB;
+  const int P = a.g.P, q0 = a.g.q0;
+  const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), P, q0);
+  if constexpr (D::kTable) {
+    // raw stored values; the fallback recomputes c from them, so no address is
+    // kept alive across the barrier
+    int32_t raw[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) raw[k] = D::raw(a.diag, xb + tile_off((uint32_t)k << w, P, q0));
+    int ok = 1;
+    if constexpr (!D::kAlwaysInTable) {
+#pragma unroll
+      for (int k = 0; k < E; ++k) ok &= (D::tab_index(raw[k]) >= 0);
+    }
+    for (uint32_t e = tid; e < (uint32_t)kTabEntries; e += blockDim.x) tab[e] = lp.tab[e];
+    bool fast;
+    if constexpr (D::kAlwaysInTable) {
+      __syncthreads();
+      fast = true;
+    } else {
+      fast = !__syncthreads_or(!ok);
+    }
+    if (fast) {
+      // groups of four elements: bounds how many table entries the scheduler
+      // keeps in flight (register pressure decides occupancy here)
+#pragma unroll
+      for (int k0 = 0; k0 < E; k0 += 4) {
+#pragma unroll
+        for (int k = k0; k < k0 + 4 && k < E; ++k) {
+          const int32_t u = D::tab_index(raw[k]);
+          const double2 h = tab[u >> 8], lo = tab[256 + (u & 255)];
+          cmul_inplace(vr[k], vi[k], fma(h.x, lo.x, -h.y * lo.y), fma(h.x, lo.y, h.y * lo.x));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const double2 f = phase_direct(lp.g, (double)raw[k] + a.diag_offset);
+        cmul_inplace(vr[k], vi[k], f.x, f.y);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const double c = D::get(a.diag, xb + tile_off((uint32_t)k << w, P, q0)) + a.diag_offset;
+      const double2 f = phase_direct(lp.g, c);
+      cmul_inplace(vr[k], vi[k], f.x, f.y);
+    }
+  }
+}
+
+// Mixer gates of one layer on the tile's active qubits, window by window.
+template <class S, int EB>
+__device__ __forceinline__ int apply_mixer(double (&vr)[1 << EB], double (&vi)[1 << EB], typename S::L* lds,
+                                           const TileGeom& g, uint32_t tid, int w, double ca, double sb) {
+  constexpr int E = 1 << EB;
+  for (int ci = 0; ci < g.nchunks; ++ci) {
+    const Chunk ch = g.chunk[ci];
+    if (ch.w != w) {
+      exchange_c<S, EB>(vr, vi, lds, tid, w, ch.w);
+      w = ch.w;
+    }
+#pragma unroll
+    for (int j = 0; j < EB; ++j) {
+      if (j >= ch.jlo && j < ch.jhi) {
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+          if (!(k & (1 << j))) rx_pair(vr[k], vi[k], vr[k | (1 << j)], vi[k | (1 << j)], ca, sb);
+        }
+      }
+    }
+  }
+  return w;
+}
+
+// (E, norm) partial sums of the thread's elements.
+template <class D, int EB>
+__device__ __forceinline__ void expv_partials(const double (&vr)[1 << EB], const double (&vi)[1 << EB],
+                                              const SweepArgs& a, uint64_t base, uint32_t tid, int w,
+                                              double& e_part, double& n_part) {
+  const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g.P, a.g.q0);
+#pragma unroll
+  for (int k = 0; k < (1 << EB); ++k) {
+    const double c = D::get(a.diag, xb + tile_off((uint32_t)k << w, a.g.P, a.g.q0)) + a.diag_offset;
+    const double pr = vr[k] * vr[k] + vi[k] * vi[k];
+    e_part += pr * c;
+    n_part += pr;
+  }
+}
+
+// One HBM sweep of one layer (multi-tile states).  The flags are compile-time
+// so each launch carries only the code it runs:
+//   INIT   generate |+> in registers instead of loading the state
+//   PHASE  apply the layer's phase before the mixer gates
+//   EXPV   emit per-workgroup (E, norm) partials of the result
+template <class S, class D, int EB, bool INIT, bool PHASE, bool EXPV>
+__global__ void __launch_bounds__(512, S::kMinWavesPerSimd) qaoa_sweep_kernel(const SweepArgs a) {
   constexpr int E = 1 << EB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   typename S::L* lds = reinterpret_cast<typename S::L*>(smem_raw);
+  double2* tab = reinterpret_cast<double2*>(smem_raw + (1u << a.g.tb) * S::kBytes);
   const uint32_t tid = threadIdx.x;
   const int P = a.g.P, q0 = a.g.q0;
   const uint64_t base = block_base(blockIdx.x, a.g.tb, P, q0);
+  const uint32_t set = blockIdx.y;
+  void* psi = reinterpret_cast<char*>(a.psi) + (uint64_t)set * a.set_stride_bytes;
+  const LayerParams lp = layer_params(a, set, 0);
 
+  double vr[E], vi[E];
+  const int w_load = a.g.tb - EB;
+  int w = w_load;
+  // EXPV: the cost values are read with the state, in the coalesced load
+  // mapping, and the tile returns to that mapping for the reduction
+  typename D::RawT cv[EXPV ? E : 1];
+  {
+    const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), P, q0);
+    if constexpr (INIT) {
+#pragma unroll
+      for (int k = 0; k < E; ++k) { vr[k] = a.amp0; vi[k] = 0.0; }
+    } else {
+#pragma unroll
+      for (int k = 0; k < E; ++k) S::load(psi, xb + tile_off((uint32_t)k << w, P, q0), vr[k], vi[k]);
+    }
+    if constexpr (EXPV) {
+#pragma unroll
+      for (int k = 0; k < E; ++k) cv[k] = D::load_raw(a.diag, xb + tile_off((uint32_t)k << w, P, q0));
+    }
+  }
+  if constexpr (PHASE) apply_phase<S, D, EB>(vr, vi, a, lp, base, tid, w, tab);
+  w = apply_mixer<S, EB>(vr, vi, lds, a.g, tid, w, lp.ca, lp.sb);
+
+  double e_part = 0.0, n_part = 0.0;
+  const int w_out = EXPV ? w_load : a.g.w_store;
+  if (w != w_out) {
+    exchange_c<S, EB>(vr, vi, lds, tid, w, w_out);
+    w = w_out;
+  }
+  if constexpr (EXPV) {
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const double pr = vr[k] * vr[k] + vi[k] * vi[k];
+      e_part += pr * (D::value(cv[k]) + a.diag_offset);
+      n_part += pr;
+    }
+  }
+  {
+    const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), P, q0);
+#pragma unroll
+    for (int k = 0; k < E; ++k) S::store(psi, xb + tile_off((uint32_t)k << w, P, q0), vr[k], vi[k]);
+  }
+  if constexpr (EXPV) {
+    block_sum2(e_part, n_part, reinterpret_cast<double*>(smem_raw));
+    if (tid == 0) {
+      double* part = a.partials + (uint64_t)set * a.partials_stride;
+      part[2 * (uint64_t)blockIdx.x] = e_part;
+      part[2 * (uint64_t)blockIdx.x + 1] = n_part;
+    }
+  }
+}
+
+// Whole state in one tile (n <= tile bits): up to kMaxLayersPerLaunch layers
+// in one launch, one workgroup.  Latency-bound; runtime flags.
+template <class S, class D, int EB>
+__global__ void __launch_bounds__(512) qaoa_tile_kernel(const SweepArgs a) {
+  constexpr int E = 1 << EB;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  typename S::L* lds = reinterpret_cast<typename S::L*>(smem_raw);
+  double2* tab = reinterpret_cast<double2*>(smem_raw + (1u << a.g.tb) * S::kBytes);
+  const uint32_t tid = threadIdx.x;
+  const uint32_t set = blockIdx.x;
+  void* psi = reinterpret_cast<char*>(a.psi) + (uint64_t)set * a.set_stride_bytes;
   double vr[E], vi[E];
   int w = a.g.tb - EB;
   if (a.flags & F_INIT) {
@@ -226,86 +474,46 @@ __global__ void __launch_bounds__(512) qaoa_sweep_kernel(const SweepArgs a) {
     for (int k = 0; k < E; ++k) { vr[k] = a.amp0; vi[k] = 0.0; }
   } else {
 #pragma unroll
-    for (int k = 0; k < E; ++k) S::load(a.psi, base + tile_off(tmap<EB>(tid, k, w), P, q0), vr[k], vi[k]);
+    for (int k = 0; k < E; ++k) S::load(psi, tmap<EB>(tid, k, w), vr[k], vi[k]);
   }
-
-  const uint32_t tile_bytes = (1u << a.g.tb) * S::kBytes;
-  double2* tab = reinterpret_cast<double2*>(smem_raw + tile_bytes);
   for (int l = 0; l < a.nlayers; ++l) {
-    if (a.flags & F_PHASE) {
-      const double g = a.gamma[l];
-      if constexpr (D::kTable) {
-        // stage this layer's tables in LDS (the previous layer's reads of the
-        // tables finished before the exchanges that followed them)
-        if (l > 0) __syncthreads();
-        for (uint32_t e = tid; e < (uint32_t)kTabEntries; e += blockDim.x) tab[e] = a.ptab[(size_t)l * kTabEntries + e];
-        __syncthreads();
-      }
-#pragma unroll
-      for (int k = 0; k < E; ++k) {
-        const uint64_t x = base + tile_off(tmap<EB>(tid, k, w), P, q0);
-        double cs, sn;  // exp(-i g c) = cs + i sn
-        const int32_t u = D::tab_index(D::raw(a.diag, x));
-        if (D::kTable && u >= 0) {
-          const double2 h = tab[u >> 8], lo = tab[256 + (u & 255)];
-          cs = fma(h.x, lo.x, -h.y * lo.y);
-          sn = fma(h.x, lo.y, h.y * lo.x);
-        } else {
-          const double c = D::get(a.diag, x) + a.diag_offset;
-          double s0;
-          sincos(g * c, &s0, &cs);
-          sn = -s0;
-        }
-        const double r = vr[k], im = vi[k];
-        vr[k] = fma(cs, r, -sn * im);
-        vi[k] = fma(cs, im, sn * r);
-      }
-    }
-    const double ca = a.ca[l], sb = a.sb[l];
-    for (int ci = 0; ci < a.g.nchunks; ++ci) {
-      const Chunk ch = a.g.chunk[ci];
-      if (ch.w != w) {
-        exchange_c<S, EB>(vr, vi, lds, tid, w, ch.w);
-        w = ch.w;
-      }
-#pragma unroll
-      for (int j = 0; j < EB; ++j) {
-        if (j >= ch.jlo && j < ch.jhi) {
-#pragma unroll
-          for (int k = 0; k < E; ++k) {
-            if (!(k & (1 << j))) rx_pair(vr[k], vi[k], vr[k | (1 << j)], vi[k | (1 << j)], ca, sb);
-          }
-        }
-      }
-    }
+    // the previous layer's table reads must finish before the table is restaged
+    if (l > 0) __syncthreads();
+    const LayerParams lp = layer_params(a, set, l);
+    apply_phase<S, D, EB>(vr, vi, a, lp, 0, tid, w, tab);
+    w = apply_mixer<S, EB>(vr, vi, lds, a.g, tid, w, lp.ca, lp.sb);
   }
-
   double e_part = 0.0, n_part = 0.0;
-  if (a.flags & F_EXPV) {
-#pragma unroll
-    for (int k = 0; k < E; ++k) {
-      const uint64_t x = base + tile_off(tmap<EB>(tid, k, w), P, q0);
-      const double c = D::get(a.diag, x) + a.diag_offset;
-      const double pr = vr[k] * vr[k] + vi[k] * vi[k];
-      e_part += pr * c;
-      n_part += pr;
-    }
-  }
-
+  if (a.flags & F_EXPV) expv_partials<D, EB>(vr, vi, a, 0, tid, w, e_part, n_part);
   if (w != a.g.w_store) {
     exchange_c<S, EB>(vr, vi, lds, tid, w, a.g.w_store);
     w = a.g.w_store;
   }
 #pragma unroll
-  for (int k = 0; k < E; ++k) S::store(a.psi, base + tile_off(tmap<EB>(tid, k, w), P, q0), vr[k], vi[k]);
-
+  for (int k = 0; k < E; ++k) S::store(psi, tmap<EB>(tid, k, w), vr[k], vi[k]);
   if (a.flags & F_EXPV) {
     block_sum2(e_part, n_part, reinterpret_cast<double*>(smem_raw));
     if (tid == 0) {
-      a.partials[2 * (uint64_t)blockIdx.x] = e_part;
-      a.partials[2 * (uint64_t)blockIdx.x + 1] = n_part;
+      double* part = a.partials + (uint64_t)set * a.partials_stride;
+      part[0] = e_part;
+      part[1] = n_part;
     }
   }
+}
+
+// ----------------------------------------------------------------------------
+// batched evaluation helpers
+// ----------------------------------------------------------------------------
+
+// out[2 s + {0,1}] = fixed-order sum of set s's `count` partial pairs.
+__global__ void __launch_bounds__(256) finalize_batch_kernel(const double* partials, uint64_t count,
+                                                             uint64_t stride, double* out) {
+  __shared__ double scratch[16];
+  const double* part = partials + (uint64_t)blockIdx.x * stride;
+  double e = 0.0, q = 0.0;
+  for (uint64_t i = threadIdx.x; i < count; i += blockDim.x) { e += part[2 * i]; q += part[2 * i + 1]; }
+  block_sum2(e, q, scratch);
+  if (threadIdx.x == 0) { out[2 * blockIdx.x] = e; out[2 * blockIdx.x + 1] = q; }
 }
 
 // ----------------------------------------------------------------------------

@@ -126,39 +126,89 @@ uint64_t plan_blocks(int n, const qk::TileGeom& g) { return (uint64_t)1 << (n - 
 // ---------------------------------------------------------------------------
 // typed launchers
 // ---------------------------------------------------------------------------
+// LDS bytes of a tile kernel: the tile, the phase tables when the launch
+// applies a phase with an integer cost vector, and at least the reduction
+// scratch (16 doubles, or 2 per thread for a partial wave), which is only
+// used after the tile and the tables are done with.
+template <class S, class D>
+size_t tile_lds_bytes(const qk::TileGeom& g, uint32_t threads, bool phase) {
+  const size_t tile = ((size_t)1 << g.tb) * S::kBytes;
+  const size_t tab = (D::kTable && phase) ? qk::kTabEntries * sizeof(double2) : 0;
+  return std::max<size_t>(tile + tab, std::max<size_t>(16, 2 * threads) * sizeof(double));
+}
+
+template <class S, class D, bool INIT, bool PHASE, bool EXPV>
+void launch_sweep_f(const qk::SweepArgs& a, uint64_t blocks, uint32_t sets, hipStream_t st) {
+  const uint32_t threads = 1u << (a.g.tb - kEB);
+  const size_t lds = tile_lds_bytes<S, D>(a.g, threads, PHASE);
+  hipLaunchKernelGGL((qk::qaoa_sweep_kernel<S, D, kEB, INIT, PHASE, EXPV>), dim3((uint32_t)blocks, sets), dim3(threads),
+                     lds, st, a);
+}
+
+// One sweep of one layer.  The plans only produce these flag combinations:
+// phase sweeps (first sweep of a layer, |+> generated in layer 1) and plain or
+// reducing mixer sweeps (the reduction in the last sweep of the last layer).
+template <class S, class D>
+int launch_sweep_d(const qk::SweepArgs& a, uint64_t blocks, uint32_t sets, hipStream_t st) {
+  const bool init = a.flags & qk::F_INIT, phase = a.flags & qk::F_PHASE, expv = a.flags & qk::F_EXPV;
+  if (phase && !expv) {
+    if (init) launch_sweep_f<S, D, true, true, false>(a, blocks, sets, st);
+    else launch_sweep_f<S, D, false, true, false>(a, blocks, sets, st);
+  } else if (!init && !phase) {
+    if (expv) launch_sweep_f<S, D, false, false, true>(a, blocks, sets, st);
+    else launch_sweep_f<S, qk::DF64, false, false, false>(a, blocks, sets, st);  // does not read the cost vector
+  } else {
+    return fail(QAOA_ERR_UNSUPPORTED, "internal: sweep flag combination %d not instantiated", a.flags);
+  }
+  return QAOA_OK;
+}
+
+template <class S>
+int launch_sweep_s(const qk::SweepArgs& a, int diag_dtype, uint64_t blocks, uint32_t sets, hipStream_t st) {
+  switch (diag_dtype) {
+    case QAOA_DIAG_I32: return launch_sweep_d<S, qk::DI32>(a, blocks, sets, st);
+    case QAOA_DIAG_U16: return launch_sweep_d<S, qk::DU16>(a, blocks, sets, st);
+    default: return launch_sweep_d<S, qk::DF64>(a, blocks, sets, st);
+  }
+}
+
+// One sweep over `blocks` tiles of each of `sets` states.
+int launch_sweep(const qk::SweepArgs& a, int state_dtype, int diag_dtype, uint64_t blocks, uint32_t sets,
+                 hipStream_t st) {
+  if (state_dtype == QAOA_C128) return launch_sweep_s<qk::C128>(a, diag_dtype, blocks, sets, st);
+  return launch_sweep_s<qk::C64>(a, diag_dtype, blocks, sets, st);
+}
+
 template <class S, class D, int EB>
-void launch_sweep_t(const qk::SweepArgs& a, uint64_t blocks, hipStream_t st) {
+void launch_tile_t(const qk::SweepArgs& a, uint32_t sets, hipStream_t st) {
   const uint32_t threads = 1u << (a.g.tb - EB);
-  // tile buffer + phase tables; also the reduction scratch (16 doubles, or 2 per
-  // thread for a partial wave), which is used after the tables are done with
-  const size_t tile = ((size_t)1 << a.g.tb) * S::kBytes;
-  const size_t tab = (D::kTable && (a.flags & qk::F_PHASE)) ? qk::kTabEntries * sizeof(double2) : 0;
-  const size_t lds = std::max<size_t>(tile + tab, std::max<size_t>(16, 2 * threads) * sizeof(double));
-  hipLaunchKernelGGL((qk::qaoa_sweep_kernel<S, D, EB>), dim3((uint32_t)blocks), dim3(threads), lds, st, a);
+  const size_t lds = tile_lds_bytes<S, D>(a.g, threads, true);
+  hipLaunchKernelGGL((qk::qaoa_tile_kernel<S, D, EB>), dim3(sets), dim3(threads), lds, st, a);
 }
 
 template <class S, class D>
-void launch_sweep_d(const qk::SweepArgs& a, int eb, uint64_t blocks, hipStream_t st) {
+void launch_tile_d(const qk::SweepArgs& a, int eb, uint32_t sets, hipStream_t st) {
   switch (eb) {
-    case 1: launch_sweep_t<S, D, 1>(a, blocks, st); break;
-    case 2: launch_sweep_t<S, D, 2>(a, blocks, st); break;
-    case 3: launch_sweep_t<S, D, 3>(a, blocks, st); break;
-    default: launch_sweep_t<S, D, 4>(a, blocks, st); break;
+    case 1: launch_tile_t<S, D, 1>(a, sets, st); break;
+    case 2: launch_tile_t<S, D, 2>(a, sets, st); break;
+    case 3: launch_tile_t<S, D, 3>(a, sets, st); break;
+    default: launch_tile_t<S, D, 4>(a, sets, st); break;
   }
 }
 
 template <class S>
-void launch_sweep_s(const qk::SweepArgs& a, int diag_dtype, int eb, uint64_t blocks, hipStream_t st) {
+void launch_tile_s(const qk::SweepArgs& a, int diag_dtype, int eb, uint32_t sets, hipStream_t st) {
   switch (diag_dtype) {
-    case QAOA_DIAG_I32: launch_sweep_d<S, qk::DI32>(a, eb, blocks, st); break;
-    case QAOA_DIAG_U16: launch_sweep_d<S, qk::DU16>(a, eb, blocks, st); break;
-    default: launch_sweep_d<S, qk::DF64>(a, eb, blocks, st); break;
+    case QAOA_DIAG_I32: launch_tile_d<S, qk::DI32>(a, eb, sets, st); break;
+    case QAOA_DIAG_U16: launch_tile_d<S, qk::DU16>(a, eb, sets, st); break;
+    default: launch_tile_d<S, qk::DF64>(a, eb, sets, st); break;
   }
 }
 
-void launch_sweep(const qk::SweepArgs& a, int state_dtype, int diag_dtype, int eb, uint64_t blocks, hipStream_t st) {
-  if (state_dtype == QAOA_C128) launch_sweep_s<qk::C128>(a, diag_dtype, eb, blocks, st);
-  else launch_sweep_s<qk::C64>(a, diag_dtype, eb, blocks, st);
+// Whole-state tiles: one workgroup per state, `sets` states.
+void launch_tile(const qk::SweepArgs& a, int state_dtype, int diag_dtype, int eb, uint32_t sets, hipStream_t st) {
+  if (state_dtype == QAOA_C128) launch_tile_s<qk::C128>(a, diag_dtype, eb, sets, st);
+  else launch_tile_s<qk::C64>(a, diag_dtype, eb, sets, st);
 }
 
 template <class S, class D>
@@ -258,27 +308,27 @@ int int_stats(int n, const int32_t* data, int32_t lowmask, void* work, int64_t o
 
 constexpr size_t kStatWork = (3 * kStatBlocks + 4) * sizeof(int64_t);
 
-// Evolve workspace: [per-block (E, norm) partials][phase tables of up to
-// kMaxLayersPerLaunch layers].
-size_t partials_bytes(int n, int state_dtype) {
+// Evolve workspace layout: [per-state (E, norm) partials of the last sweep]
+// [parameter rows: 3 doubles each][phase tables: kTabEntries double2 per row].
+// A single evaluation with host angles uses kMaxLayersPerLaunch rows (one
+// chunk of layers at a time); a batch with device angles uses batch * p rows.
+struct EvolveWork {
+  size_t partials_stride;  // doubles per state
+  size_t partials_bytes, pset_bytes, tab_bytes, total;
+};
+EvolveWork evolve_work(int n, size_t states, size_t rows, int state_dtype) {
+  EvolveWork b{};
   const Plan pl = make_plan(n, state_elem_bytes(state_dtype));
   const uint64_t last = plan_blocks(n, pl.sweeps.back());
-  return 2 * sizeof(double) * std::max<uint64_t>(last, kExpectBlocks);
+  b.partials_stride = 2 * std::max<uint64_t>(last, kExpectBlocks);
+  b.partials_bytes = sizeof(double) * b.partials_stride * states;
+  b.pset_bytes = ((3 * sizeof(double) * rows + 255) / 256) * 256;
+  b.tab_bytes = rows * qk::kTabEntries * sizeof(double2);
+  b.total = b.partials_bytes + b.pset_bytes + b.tab_bytes;
+  return b;
 }
-constexpr size_t kTableBytes = (size_t)qk::kMaxLayersPerLaunch * qk::kTabEntries * sizeof(double2);
-size_t evolve_work_bytes(int n, int state_dtype) { return partials_bytes(n, state_dtype) + kTableBytes; }
-
-// Phase tables for layers [l0, l0 + nl) into `tab` (integer cost vectors only).
-int enqueue_phase_tables(double2* tab, const double* gamma, int l0, int nl, double base, hipStream_t st) {
-  qk::PhaseTableArgs t{};
-  t.out = tab;
-  t.base = base;
-  t.nlayers = nl;
-  for (int i = 0; i < nl; ++i) t.gamma[i] = gamma[l0 + i];
-  hipLaunchKernelGGL(qk::phase_table_kernel, dim3(nl), dim3(256), 0, st, t);
-  LAUNCH_CHECK("phase_table_kernel");
-  return QAOA_OK;
-}
+size_t evolve_work_bytes(int n, int state_dtype) { return evolve_work(n, 1, qk::kMaxLayersPerLaunch, state_dtype).total; }
+size_t partials_bytes(int n, int state_dtype) { return evolve_work(n, 1, 0, state_dtype).partials_bytes; }
 
 double table_base(int diag_dtype, double diag_offset) {
   return (diag_dtype == QAOA_DIAG_I32 ? qk::DI32::kTableBase : qk::DU16::kTableBase) + diag_offset;
@@ -494,6 +544,102 @@ static int enqueue_expectation(int n, const void* d_state, int sdt, const void* 
   return QAOA_OK;
 }
 
+// Enqueue p layers for `batch` states (stride 2^n elements) starting at d_states.
+// Angles come from the host arrays (batch == 1; prepared on the device in
+// chunks of kMaxLayersPerLaunch layers) or from device arrays [batch][p]
+// (prepared once).  Both use layer_prep_kernel, so a state's result does not
+// depend on which entry point or grouping produced it.
+static int enqueue_evolve(int n, int p, int batch, const double* h_gamma, const double* h_beta, const double* d_gamma,
+                          const double* d_beta, const void* d_diag, int diag_dtype, double diag_offset,
+                          void* d_states, int state_dtype, int init, double* d_out, int G, void* d_work,
+                          hipStream_t st) {
+  const uint64_t N = (uint64_t)1 << n;
+  const size_t S = state_elem_bytes(state_dtype);
+  const bool host_angles = (h_gamma != nullptr);
+  const size_t rows = host_angles ? (size_t)qk::kMaxLayersPerLaunch : (size_t)batch * (size_t)p;
+  const EvolveWork ew = evolve_work(n, (size_t)batch, rows, state_dtype);
+  char* wk = reinterpret_cast<char*>(d_work);
+  double* partials = reinterpret_cast<double*>(wk);
+  double* pset = reinterpret_cast<double*>(wk + ew.partials_bytes);
+  double2* tab = reinterpret_cast<double2*>(wk + ew.partials_bytes + ew.pset_bytes);
+  const bool use_tab = diag_dtype != QAOA_DIAG_F64;
+
+  qk::PrepArgs pa{};
+  pa.pset = pset;
+  pa.tab = use_tab ? tab : nullptr;
+  pa.base = use_tab ? table_base(diag_dtype, diag_offset) : 0.0;
+  auto prep = [&](int l0, int nl) -> int {  // host angles, layers [l0, l0 + nl)
+    pa.rows = nl;
+    for (int i = 0; i < nl; ++i) { pa.gamma[i] = h_gamma[l0 + i]; pa.beta[i] = h_beta[l0 + i]; }
+    hipLaunchKernelGGL(qk::layer_prep_kernel, dim3(nl), dim3(256), 0, st, pa);
+    LAUNCH_CHECK("layer_prep_kernel");
+    return QAOA_OK;
+  };
+  if (!host_angles) {
+    pa.gamma_d = d_gamma;
+    pa.beta_d = d_beta;
+    pa.rows = batch * p;
+    hipLaunchKernelGGL(qk::layer_prep_kernel, dim3((uint32_t)(batch * p)), dim3(256), 0, st, pa);
+    LAUNCH_CHECK("layer_prep_kernel");
+  }
+
+  const Plan pl = make_plan(n, S);
+  qk::SweepArgs a{};
+  a.diag = d_diag;
+  a.diag_offset = diag_offset;
+  a.amp0 = std::pow(2.0, -0.5 * n);
+  a.ptab = tab;
+  a.pset = pset;
+  a.p_total = host_angles ? qk::kMaxLayersPerLaunch : p;
+  a.set_stride_bytes = N * S;
+  a.partials_stride = ew.partials_stride;
+  int rc = QAOA_OK;
+  for (int s0 = 0; s0 < batch; s0 += G) {
+    const uint32_t sets = (uint32_t)std::min(G, batch - s0);
+    a.set0 = host_angles ? 0 : s0;
+    a.psi = reinterpret_cast<char*>(d_states) + (size_t)s0 * N * S;
+    a.partials = partials + (size_t)s0 * ew.partials_stride;
+    uint64_t last_blocks = 1;
+    for (int l0 = 0; l0 < p; l0 += qk::kMaxLayersPerLaunch) {
+      const int nl = std::min(qk::kMaxLayersPerLaunch, p - l0);
+      if (host_angles) {
+        rc = prep(l0, nl);
+        if (rc) return rc;
+      }
+      if (pl.single) {
+        a.g = pl.sweeps[0];
+        a.layer0 = host_angles ? 0 : l0;
+        a.nlayers = nl;
+        a.flags = qk::F_PHASE | ((l0 == 0 && init) ? qk::F_INIT : 0) | ((l0 + nl == p && d_out) ? qk::F_EXPV : 0);
+        launch_tile(a, state_dtype, diag_dtype, pl.eb, sets, st);
+        LAUNCH_CHECK("qaoa_tile_kernel");
+        continue;
+      }
+      const size_t nsw = pl.sweeps.size();
+      a.nlayers = 1;
+      for (int l = l0; l < l0 + nl; ++l) {
+        a.layer0 = host_angles ? l - l0 : l;
+        for (size_t sw = 0; sw < nsw; ++sw) {
+          a.g = pl.sweeps[sw];
+          const bool last = (l == p - 1) && (sw == nsw - 1);
+          a.flags = (sw == 0 ? qk::F_PHASE : 0) | ((sw == 0 && l == 0 && init) ? qk::F_INIT : 0) |
+                    ((last && d_out) ? qk::F_EXPV : 0);
+          last_blocks = plan_blocks(n, a.g);
+          rc = launch_sweep(a, state_dtype, diag_dtype, last_blocks, sets, st);
+          if (rc) return rc;
+          LAUNCH_CHECK("qaoa_sweep_kernel");
+        }
+      }
+    }
+    if (d_out) {
+      hipLaunchKernelGGL(qk::finalize_batch_kernel, dim3(sets), dim3(256), 0, st, (const double*)a.partials,
+                         last_blocks, (uint64_t)ew.partials_stride, d_out + 2 * (size_t)s0);
+      LAUNCH_CHECK("finalize_batch_kernel");
+    }
+  }
+  return QAOA_OK;
+}
+
 int qaoa_evolve(int n, int p, const double* gamma, const double* beta, const void* d_diag, int diag_dtype,
                 double diag_offset, size_t diag_bytes, void* d_state, int state_dtype, size_t state_bytes, int init,
                 double* d_out, void* d_work, size_t work_bytes, void* stream) {
@@ -522,69 +668,8 @@ int qaoa_evolve(int n, int p, const double* gamma, const double* beta, const voi
     return QAOA_OK;
   }
 
-  const Plan pl = make_plan(n, state_elem_bytes(state_dtype));
-  qk::SweepArgs a{};
-  a.psi = d_state;
-  a.diag = d_diag;
-  a.diag_offset = diag_offset;
-  a.amp0 = amp0;
-  double* partials = reinterpret_cast<double*>(d_work);
-  double2* tab = reinterpret_cast<double2*>(reinterpret_cast<char*>(d_work) + partials_bytes(n, state_dtype));
-  const bool use_tab = diag_dtype != QAOA_DIAG_F64;
-  const double tbase = use_tab ? table_base(diag_dtype, diag_offset) : 0.0;
-  a.ptab = tab;
-
-  if (pl.single) {
-    // whole state in one tile: up to kMaxLayersPerLaunch layers per launch
-    a.g = pl.sweeps[0];
-    for (int l0 = 0; l0 < p; l0 += qk::kMaxLayersPerLaunch) {
-      const int nl = std::min(qk::kMaxLayersPerLaunch, p - l0);
-      const bool last = (l0 + nl == p);
-      if (use_tab) {
-        const int rc2 = enqueue_phase_tables(tab, gamma, l0, nl, tbase, st);
-        if (rc2) return rc2;
-      }
-      a.flags = qk::F_PHASE | ((l0 == 0 && init) ? qk::F_INIT : 0) | ((last && d_out) ? qk::F_EXPV : 0);
-      a.nlayers = nl;
-      for (int i = 0; i < nl; ++i) {
-        a.gamma[i] = gamma[l0 + i];
-        a.ca[i] = std::cos(beta[l0 + i]);
-        a.sb[i] = std::sin(beta[l0 + i]);
-      }
-      a.partials = d_out;  // one block: its sum is the result
-      launch_sweep(a, state_dtype, diag_dtype, pl.eb, 1, st);
-      LAUNCH_CHECK("qaoa_sweep_kernel");
-    }
-    return QAOA_OK;
-  }
-
-  const size_t nsw = pl.sweeps.size();
-  for (int l = 0; l < p; ++l) {
-    if (use_tab && l % qk::kMaxLayersPerLaunch == 0) {
-      const int rc2 = enqueue_phase_tables(tab, gamma, l, std::min(qk::kMaxLayersPerLaunch, p - l), tbase, st);
-      if (rc2) return rc2;
-    }
-    a.ptab = tab + (size_t)(l % qk::kMaxLayersPerLaunch) * qk::kTabEntries;
-    for (size_t s = 0; s < nsw; ++s) {
-      a.g = pl.sweeps[s];
-      a.nlayers = 1;
-      a.gamma[0] = gamma[l];
-      a.ca[0] = std::cos(beta[l]);
-      a.sb[0] = std::sin(beta[l]);
-      const bool last = (l == p - 1) && (s == nsw - 1);
-      a.flags = (s == 0 ? qk::F_PHASE : 0) | ((s == 0 && l == 0 && init) ? qk::F_INIT : 0) |
-                ((last && d_out) ? qk::F_EXPV : 0);
-      a.partials = partials;
-      const uint64_t blocks = plan_blocks(n, a.g);
-      launch_sweep(a, state_dtype, diag_dtype, pl.eb, blocks, st);
-      LAUNCH_CHECK("qaoa_sweep_kernel");
-      if (last && d_out) {
-        hipLaunchKernelGGL(qk::finalize_kernel, dim3(1), dim3(256), 0, st, (const double*)partials, blocks, d_out);
-        LAUNCH_CHECK("finalize_kernel");
-      }
-    }
-  }
-  return QAOA_OK;
+  return enqueue_evolve(n, p, 1, gamma, beta, nullptr, nullptr, d_diag, diag_dtype, diag_offset, d_state, state_dtype,
+                        init, d_out, 1, d_work, st);
 }
 
 int qaoa_expectation(int n, const void* d_state, int state_dtype, size_t state_bytes, const void* d_diag,
@@ -598,6 +683,60 @@ int qaoa_expectation(int n, const void* d_state, int state_dtype, size_t state_b
   if (!d_work || work_bytes < need) return fail(QAOA_ERR_NOMEM, "workspace too small: need %zu bytes", need);
   return enqueue_expectation(n, d_state, state_dtype, d_diag, diag_dtype, diag_offset, d_out, d_work,
                              reinterpret_cast<hipStream_t>(stream));
+}
+
+int qaoa_batch_workspace_bytes(int n, int p, int batch, int state_dtype, int diag_dtype, size_t* bytes) {
+  if (!bytes) return fail(QAOA_ERR_INVALID, "bytes is NULL");
+  if (n < 1 || n > QAOA_MAX_QUBITS) return fail(QAOA_ERR_INVALID, "n=%d out of range [1, %d]", n, QAOA_MAX_QUBITS);
+  if (p < 0 || batch < 1) return fail(QAOA_ERR_INVALID, "need p >= 0 and batch >= 1");
+  if (!valid_state_dtype(state_dtype)) return fail(QAOA_ERR_INVALID, "bad state dtype %d", state_dtype);
+  if (!valid_diag_dtype(diag_dtype)) return fail(QAOA_ERR_INVALID, "bad diag dtype %d", diag_dtype);
+  *bytes = evolve_work(n, (size_t)batch, (size_t)batch * (size_t)p, state_dtype).total;
+  return QAOA_OK;
+}
+
+int qaoa_evolve_batch(int n, int p, int batch, const double* d_gamma, const double* d_beta, const void* d_diag,
+                      int diag_dtype, double diag_offset, size_t diag_bytes, void* d_states, int state_dtype,
+                      size_t states_bytes, int init, double* d_out, int sets_per_pass, void* d_work,
+                      size_t work_bytes, void* stream) {
+  if (n < 1 || n > QAOA_MAX_QUBITS) return fail(QAOA_ERR_INVALID, "n=%d out of range [1, %d]", n, QAOA_MAX_QUBITS);
+  if (batch < 1) return fail(QAOA_ERR_INVALID, "batch must be >= 1");
+  if (p < 0) return fail(QAOA_ERR_INVALID, "p < 0");
+  if (p > 0 && (!d_gamma || !d_beta)) return fail(QAOA_ERR_INVALID, "d_gamma/d_beta is NULL");
+  if (sets_per_pass < 0) return fail(QAOA_ERR_INVALID, "sets_per_pass < 0");
+  if (init != 0 && init != 1) return fail(QAOA_ERR_INVALID, "init must be 0 or 1");
+  const uint64_t N = (uint64_t)1 << n;
+  int rc = validate_common(n, d_diag, diag_dtype, diag_offset, diag_bytes, d_states, state_dtype,
+                           states_bytes / (size_t)batch);
+  if (rc) return rc;
+  const size_t S = state_elem_bytes(state_dtype);
+  if (states_bytes < (size_t)batch * N * S)
+    return fail(QAOA_ERR_NOMEM, "states buffer has %zu bytes, needs %llu", states_bytes,
+                (unsigned long long)((size_t)batch * N * S));
+  const size_t need = evolve_work(n, (size_t)batch, (size_t)batch * (size_t)std::max(p, 0), state_dtype).total;
+  if (!d_work || work_bytes < need) return fail(QAOA_ERR_NOMEM, "workspace too small: need %zu bytes", need);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int G = (sets_per_pass == 0 || sets_per_pass > batch) ? std::min(batch, 65535) : std::min(sets_per_pass, 65535);
+  if (p == 0) {
+    const double amp0 = std::pow(2.0, -0.5 * n);
+    for (int s = 0; s < batch; ++s) {
+      void* psi = reinterpret_cast<char*>(d_states) + (size_t)s * N * S;
+      if (init) {
+        if (state_dtype == QAOA_C128)
+          hipLaunchKernelGGL((qk::fill_state_kernel<qk::C128>), dim3(grid_for(N, 256, 8192)), dim3(256), 0, st, psi, N, amp0);
+        else
+          hipLaunchKernelGGL((qk::fill_state_kernel<qk::C64>), dim3(grid_for(N, 256, 8192)), dim3(256), 0, st, psi, N, amp0);
+        LAUNCH_CHECK("fill_state_kernel");
+      }
+      if (d_out) {
+        rc = enqueue_expectation(n, psi, state_dtype, d_diag, diag_dtype, diag_offset, d_out + 2 * s, d_work, st);
+        if (rc) return rc;
+      }
+    }
+    return QAOA_OK;
+  }
+  return enqueue_evolve(n, p, batch, nullptr, nullptr, d_gamma, d_beta, d_diag, diag_dtype, diag_offset, d_states,
+                        state_dtype, init, d_out, G, d_work, st);
 }
 
 int qaoa_plan_describe(int n, int state_dtype, int elem_bytes, int* out, int cap) {

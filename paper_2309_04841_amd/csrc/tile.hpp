@@ -52,7 +52,16 @@ __device__ __forceinline__ uint32_t tmap(uint32_t tid, uint32_t k, int w) {
   return lo | (k << w) | ((tid >> w) << (w + EB));
 }
 
-// Global offset of tile element t relative to the block base.
+// Thread part of the window-w mapping: t(tid, k, w) = thr(tid, w) | k << w.
+template <int EB>
+__device__ __forceinline__ uint32_t thr_part(uint32_t tid, int w) {
+  return (tid & ((1u << w) - 1u)) | ((tid >> w) << (w + EB));
+}
+
+// Global offset of tile element t relative to the block base.  tile_off maps
+// tile bits to disjoint global bits, so tile_off(a | b) = tile_off(a) +
+// tile_off(b) for disjoint a, b: addresses split into a per-thread part and a
+// per-register part that is uniform across the workgroup.
 __device__ __forceinline__ uint64_t tile_off(uint32_t t, int P, int q0) {
   const uint32_t pm = (1u << P) - 1u;
   return (uint64_t)(t & pm) | ((uint64_t)(t >> P) << q0);
@@ -66,12 +75,46 @@ __device__ __forceinline__ uint64_t block_base(uint64_t b, int tb, int P, int q0
   return (blo << P) | (bhi << (q0 + tb - P));
 }
 
-// LDS position of tile element t: XOR-swizzle of the low bits with the next
-// ones, so that every window's access pattern spreads a wave over all banks.
+// LDS position of tile element t: pos = t ^ L(t >> S), L linear over GF(2)
+// into the low S bits (so pos is a permutation of the tile).  The maps are
+// chosen so that every register window's access pattern is free of bank
+// conflicts (64 banks x 4 B): for 16-byte elements each group of 16 lanes, for
+// 8-byte elements each group of 32 lanes, hits distinct banks.  Linearity also
+// splits pos(thr | k << w) = pos(thr) ^ pos(k << w) into a per-thread part and
+// a workgroup-uniform part.
+template <int ELEM_BYTES>
+struct Swz;
+template <>
+struct Swz<16> {
+  static constexpr int kShift = 4;
+  static constexpr int kCols = 4;
+  __host__ __device__ static constexpr uint32_t col(int j) { return 1u << j; }
+};
+template <>
+struct Swz<8> {
+  static constexpr int kShift = 5;
+  static constexpr int kCols = 9;
+  __host__ __device__ static constexpr uint32_t col(int j) {
+    constexpr uint32_t c[9] = {2, 28, 8, 25, 28, 1, 17, 5, 16};
+    return c[j];
+  }
+};
+template <>
+struct Swz<4> {
+  static constexpr int kShift = 5;
+  static constexpr int kCols = 5;
+  __host__ __device__ static constexpr uint32_t col(int j) { return 1u << j; }
+};
+template <>
+struct Swz<2> : Swz<4> {};
+
 template <int ELEM_BYTES>
 __device__ __forceinline__ uint32_t swz(uint32_t t) {
-  if constexpr (ELEM_BYTES >= 16) return t ^ ((t >> 4) & 15u);
-  else return t ^ ((t >> 5) & 31u);
+  using Z = Swz<ELEM_BYTES>;
+  uint32_t x = 0;
+#pragma unroll
+  for (int j = 0; j < Z::kCols; ++j) x ^= ((t >> (Z::kShift + j)) & 1u) ? Z::col(j) : 0u;
+  return t ^ x;
 }
 
 }  // namespace qk

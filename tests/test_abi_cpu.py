@@ -40,8 +40,8 @@ def test_version_and_last_error():
 
 
 def test_workspace_bytes():
-    # per-block (E, norm) partials of the last sweep + phase tables of 32 layers
-    assert _lib.workspace_bytes(_lib.QAOA_OP_EVOLVE, 26, _lib.QAOA_C128) == 16 * (1 << 14) + 32 * 512 * 16
+    # per-block (E, norm) partials of the last sweep + parameter rows and phase tables of 32 layers
+    assert _lib.workspace_bytes(_lib.QAOA_OP_EVOLVE, 26, _lib.QAOA_C128) == 16 * (1 << 14) + 3 * 8 * 32 + 32 * 512 * 16
     assert _lib.workspace_bytes(_lib.QAOA_OP_PRECOMPUTE, 20, diag_dtype=_lib.QAOA_DIAG_F64) == 0
     assert _lib.workspace_bytes(_lib.QAOA_OP_PRECOMPUTE, 20, diag_dtype=_lib.QAOA_DIAG_U16) >= 4 << 20
     with pytest.raises(_lib.QaoaError):
@@ -147,8 +147,34 @@ def block_base(b, tb, P, q0):
     return ((b & ((1 << nlow) - 1)) << P) | ((b >> nlow) << (q0 + tb - P))
 
 
+# LDS swizzle pos = t ^ L(t >> S), L given by its columns (GF(2)-linear)
+SWZ = {16: (4, [1, 2, 4, 8]), 8: (5, [2, 28, 8, 25, 28, 1, 17, 5, 16]),
+       4: (5, [1, 2, 4, 8, 16]), 2: (5, [1, 2, 4, 8, 16])}
+
+
 def swz(t, elem_bytes):
-    return t ^ ((t >> 4) & 15) if elem_bytes >= 16 else t ^ ((t >> 5) & 31)
+    shift, cols = SWZ[elem_bytes]
+    t = np.asarray(t)
+    x = np.zeros_like(t)
+    for j, c in enumerate(cols):
+        x ^= ((t >> (shift + j)) & 1) * c
+    return t ^ x
+
+
+def bank_conflict_degree(elem_bytes, tb, w, eb=4):
+    """Worst number of accesses to one 4-byte bank (64 banks) within a group of
+    lanes served together (256 B per group), over all registers k."""
+    group = min(64, 256 // elem_bytes)
+    nthreads = 1 << (tb - eb)
+    worst = 1
+    for k in range(1 << eb):
+        for g0 in range(0, min(64, nthreads), group):
+            tid = np.arange(g0, min(g0 + group, nthreads))
+            pos = swz(tmap(tid, k, w, eb), elem_bytes)
+            words = (pos * elem_bytes // 4)[:, None] + np.arange(max(1, elem_bytes // 4))[None, :]
+            counts = np.bincount((words % 64).ravel(), minlength=64)
+            worst = max(worst, int(counts.max()))
+    return worst
 
 
 def _check_plan(n, plan, elem_bytes, emulate):
@@ -208,3 +234,19 @@ def test_headline_plans_sweep_counts():
     assert len(_lib.plan_describe(26, _lib.QAOA_C128)["sweeps"]) == 3
     assert len(_lib.plan_describe(31, _lib.QAOA_C64)["sweeps"]) == 3
     assert _lib.plan_describe(12, _lib.QAOA_C128)["single"]
+
+
+@pytest.mark.parametrize("sdt,elem", [(_lib.QAOA_C128, 16), (_lib.QAOA_C64, 8)])
+def test_lds_swizzle_conflict_free(sdt, elem):
+    # every register window that any state plan uses is free of LDS bank conflicts
+    used = set()
+    for n in range(1, _lib.QAOA_MAX_QUBITS + 1):
+        plan = _lib.plan_describe(n, sdt)
+        for sw in plan["sweeps"]:
+            if sw["tb"] - plan["eb"] < 6:
+                continue  # fewer than 64 threads: single partial wave
+            for w in {c[0] for c in sw["chunks"]} | {sw["w_store"], sw["tb"] - plan["eb"]}:
+                used.add((sw["tb"], w))
+    assert used
+    for tb, w in sorted(used):
+        assert bank_conflict_degree(elem, tb, w) == 1, (tb, w)
