@@ -181,22 +181,38 @@ int qaoa_evolve_batch(int n, int p, int batch, const double *d_gamma, const doub
 int qaoa_batch_workspace_bytes(int n, int p, int batch, int state_dtype, int diag_dtype, size_t *bytes);
 
 /*
- * qaoa_grad -- E and its gradient with respect to gamma[0..p) and beta[0..p)
- * by reverse-mode evolution (adjoint method).  d_out receives 1 + 2p doubles:
- * E, dE/dgamma[0..p), dE/dbeta[0..p).  d_state and d_adj are two caller-owned
- * state buffers (each 2^n elements of state_dtype); on return d_state holds the
- * forward state at layer p.  This build returns QAOA_ERR_UNSUPPORTED after
- * validating the arguments.
+ * qaoa_grad -- E and its gradient with respect to the layer angles, the
+ * quantities an outer optimiser needs (Section 2: the angles are chosen to
+ * minimise <gamma beta|C|gamma beta>).  Reverse-mode (adjoint) evaluation:
+ * one forward pass (Algorithm 3), then the layers are undone in reverse order
+ * on the state and on lambda = C psi_p together, accumulating
+ *   dE/dbeta_l  = 2 Im <lambda| sum_i X_i |psi>   (at layer l's output)
+ *   dE/dgamma_l = 2 Im <lambda| C |psi>           (after undoing layer l's mixer).
+ *
+ *   n, p        1 <= n <= QAOA_MAX_QUBITS, p >= 1; gamma, beta host arrays of p
+ *   d_state     device, 2^n of state_dtype: overwritten (on return it holds the
+ *               uncomputed state, |+>^n up to rounding)
+ *   d_adj       device, 2^n of state_dtype, a second state buffer (scratch, must
+ *               not alias d_state)
+ *   d_out       device, 1 + 2p doubles: E, dE/dgamma[0..p), dE/dbeta[0..p)
+ *   d_work      device, qaoa_grad_workspace_bytes(n, p, ...) bytes
+ * Deterministic (fixed reduction order).  Memory traffic is about three times
+ * that of qaoa_evolve.
  */
 int qaoa_grad(int n, int p, const double *gamma, const double *beta,
               const void *d_diag, int diag_dtype, double diag_offset, size_t diag_bytes,
               void *d_state, void *d_adj, int state_dtype, size_t state_bytes,
               double *d_out, void *d_work, size_t work_bytes, void *stream);
 
+/* Workspace bytes qaoa_grad needs. */
+int qaoa_grad_workspace_bytes(int n, int p, int state_dtype, int diag_dtype, size_t *bytes);
+
 /*
- * qaoa_plan_describe -- diagnostic: the HBM sweep plan qaoa_evolve uses for n
- * qubits of state_dtype (the same planner lays out the precompute transform for
- * an element size of elem_bytes when state_dtype < 0).  Writes up to `cap` ints:
+ * qaoa_plan_describe -- diagnostic: the HBM sweep plan used for n qubits.
+ * kind 0: qaoa_evolve / qaoa_evolve_batch sweeps for state_dtype;
+ * kind 1: the reverse sweeps of qaoa_grad for state_dtype;
+ * kind 2: the cost-vector transform for elements of elem_bytes (2, 4 or 8).
+ * Writes up to `cap` ints:
  *   [0] number of sweeps S, [1] register bits per thread EB, [2] 1 if the whole
  *   vector is one tile (all layers in one launch), then per sweep:
  *   tb, P, q0, w_store, nchunks, and nchunks triples (w, jlo, jhi).
@@ -204,7 +220,7 @@ int qaoa_grad(int n, int p, const double *gamma, const double *beta,
  * [q0, q0+tb-P); a chunk butterflies tile bits [w+jlo, w+jhi).
  * Returns the number of ints needed (may exceed cap), or -QAOA_ERR_INVALID.
  */
-int qaoa_plan_describe(int n, int state_dtype, int elem_bytes, int *out, int cap);
+int qaoa_plan_describe(int kind, int n, int state_dtype, int elem_bytes, int *out, int cap);
 
 #ifdef __cplusplus
 }

@@ -13,6 +13,7 @@ Functions and the passages they follow:
   diag_maxcut     Section 2, MaxCut: minus the (weighted) cut
   evolve          Algorithm 3 with Section 3.2's gate exp(-i beta X) per qubit
   expectation     Section 3.1: E = sum |psi|^2 c (compensated), plus sum |psi|^2
+  grad            dE/dgamma, dE/dbeta by the adjoint method (reverse Algorithm 3)
 All functions are pinned by tests against closed forms, library routines,
 brute force and invariants (see tests/test_oracle_*.py).
 """
@@ -61,6 +62,7 @@ def _load():
     lib.oracle_apply_mixer.argtypes = [ctypes.c_int, ctypes.c_double, P]
     lib.oracle_qaoa_evolve.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, P]
     lib.oracle_expectation.argtypes = [ctypes.c_int, P, P, P]
+    lib.oracle_qaoa_grad.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P]
     _lib = lib
     return lib
 
@@ -158,3 +160,22 @@ def expectation(n: int, psi, c):
 def qaoa_expectation(n: int, c, gamma, beta) -> float:
     """Convenience: E after p layers from |+>^n."""
     return expectation(n, evolve(n, c, gamma, beta), c)[0]
+
+
+def apply_rx(n: int, q: int, beta: float, psi: np.ndarray) -> np.ndarray:
+    """One mixer gate exp(-i beta X_q) on a copy of psi."""
+    out = np.ascontiguousarray(psi, dtype=np.complex128).copy()
+    _load().oracle_apply_rx(n, int(q), float(beta), _ptr(out.view(np.float64)))
+    return out
+
+
+def grad(n: int, c, gamma, beta):
+    """(E, dE/dgamma[p], dE/dbeta[p]) from |+>^n, adjoint method, FP64."""
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    g = np.ascontiguousarray(np.atleast_1d(gamma), dtype=np.float64)
+    b = np.ascontiguousarray(np.atleast_1d(beta), dtype=np.float64)
+    p = len(g)
+    out = np.zeros(1 + 2 * p, dtype=np.float64)
+    work = np.empty(4 << n, dtype=np.float64)
+    _load().oracle_qaoa_grad(n, p, _ptr(c), _ptr(g), _ptr(b), _ptr(out), _ptr(work))
+    return float(out[0]), out[1:1 + p].copy(), out[1 + p:].copy()

@@ -12,6 +12,9 @@
  *                          applied as in Algorithm 3 (phase, then mixer, layer 1 first)
  *   - mixer                Section 3.2: exp(-i beta sum_i X_i) = prod_i (cos b I - i sin b X_i)
  *   - objective            Section 3.1: E = sum_x |psi_x|^2 c_x
+ *   - gradient             dE/dgamma_l, dE/dbeta_l of that objective (the parameters
+ *                          an outer optimiser varies, Section 2), by reverse-mode
+ *                          (adjoint) differentiation of Algorithm 3
  *
  * Conventions (readings of the paper, see the design notes):
  *   - variable i <-> bit i of the basis index x (0-based), spin s_i = 1 - 2*bit_i(x);
@@ -204,4 +207,52 @@ void oracle_expectation(int n, const double *psi, const double *c, double *out)
     }
     out[0] = e + ec;
     out[1] = q + qc;
+}
+
+/* Gradient of E = <psi_p|C|psi_p> with respect to gamma[0..p) and beta[0..p),
+ * by the adjoint method (exact up to rounding):
+ *   lambda = C psi_p; for l = p..1:
+ *     dE/dbeta_l  = 2 Im <lambda| sum_i X_i |psi>        (psi, lambda after layer l)
+ *     undo the mixer of layer l on psi and lambda (gate with -beta_l)
+ *     dE/dgamma_l = 2 Im <lambda| C |psi>
+ *     undo the phase of layer l on psi and lambda (angle -gamma_l)
+ * out[0] = E, out[1 + l] = dE/dgamma_l, out[1 + p + l] = dE/dbeta_l.
+ * work: 4 * 2^n doubles (two states). */
+void oracle_qaoa_grad(int n, int p, const double *c, const double *gamma, const double *beta,
+                      double *out, double *work)
+{
+    const int64_t N = (int64_t)1 << n;
+    double *psi = work, *lam = work + 2 * N;
+    double eo[2];
+    oracle_qaoa_evolve(n, p, c, gamma, beta, 1, psi);
+    oracle_expectation(n, psi, c, eo);
+    out[0] = eo[0];
+    for (int64_t x = 0; x < N; ++x) {
+        lam[2 * x] = c[x] * psi[2 * x];
+        lam[2 * x + 1] = c[x] * psi[2 * x + 1];
+    }
+    for (int l = p - 1; l >= 0; --l) {
+        double sb = 0.0;
+        for (int q = 0; q < n; ++q) {
+            const int64_t bit = (int64_t)1 << q;
+            double sq = 0.0;
+#pragma omp parallel for reduction(+ : sq) schedule(static)
+            for (int64_t x = 0; x < N; ++x) {
+                const int64_t y = x ^ bit;
+                /* Im(conj(lam_x) psi_y) */
+                sq += lam[2 * x] * psi[2 * y + 1] - lam[2 * x + 1] * psi[2 * y];
+            }
+            sb += sq;
+        }
+        out[1 + p + l] = 2.0 * sb;
+        oracle_apply_mixer(n, -beta[l], psi);
+        oracle_apply_mixer(n, -beta[l], lam);
+        double sg = 0.0;
+#pragma omp parallel for reduction(+ : sg) schedule(static)
+        for (int64_t x = 0; x < N; ++x)
+            sg += c[x] * (lam[2 * x] * psi[2 * x + 1] - lam[2 * x + 1] * psi[2 * x]);
+        out[1 + l] = 2.0 * sg;
+        oracle_apply_phase(n, c, -gamma[l], psi);
+        oracle_apply_phase(n, c, -gamma[l], lam);
+    }
 }

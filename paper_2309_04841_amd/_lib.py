@@ -22,7 +22,7 @@ QAOA_MAX_QUBITS = 34
 
 EXPORTS = ("qaoa_version", "qaoa_last_error", "qaoa_workspace_bytes", "qaoa_precompute_diag",
            "qaoa_evolve", "qaoa_expectation", "qaoa_grad", "qaoa_plan_describe", "qaoa_evolve_batch",
-           "qaoa_batch_workspace_bytes")
+           "qaoa_batch_workspace_bytes", "qaoa_grad_workspace_bytes")
 
 _STATUS_NAMES = {0: "QAOA_OK", 1: "QAOA_ERR_INVALID", 2: "QAOA_ERR_RANGE", 3: "QAOA_ERR_NOMEM",
                  4: "QAOA_ERR_DEVICE", 5: "QAOA_ERR_UNSUPPORTED"}
@@ -55,7 +55,9 @@ def _load() -> ctypes.CDLL:
     lib.qaoa_grad.restype = I
     lib.qaoa_grad.argtypes = [I, I, P, P, P, I, D, SZ, P, P, I, SZ, P, P, SZ, P]
     lib.qaoa_plan_describe.restype = I
-    lib.qaoa_plan_describe.argtypes = [I, I, I, P, I]
+    lib.qaoa_plan_describe.argtypes = [I, I, I, I, P, I]
+    lib.qaoa_grad_workspace_bytes.restype = I
+    lib.qaoa_grad_workspace_bytes.argtypes = [I, I, I, I, ctypes.POINTER(SZ)]
     lib.qaoa_evolve_batch.restype = I
     lib.qaoa_evolve_batch.argtypes = [I, I, I, P, P, P, I, D, SZ, P, I, SZ, I, P, I, P, SZ, P]
     lib.qaoa_batch_workspace_bytes.restype = I
@@ -121,13 +123,19 @@ def _f64(values) -> ctypes.Array:
     return (ctypes.c_double * max(1, len(vals)))(*vals)
 
 
-def plan_describe(n: int, state_dtype: int = QAOA_C128, elem_bytes: int = 0) -> dict:
-    """The sweep plan as a dict: {'eb', 'single', 'sweeps': [{'tb','P','q0','w_store','chunks'}]}."""
-    need = lib.qaoa_plan_describe(n, state_dtype, elem_bytes, None, 0)
+PLAN_EVOLVE, PLAN_ADJOINT, PLAN_TRANSFORM = 0, 1, 2
+
+
+def plan_describe(n: int, state_dtype: int = QAOA_C128, elem_bytes: int = 0, kind: int | None = None) -> dict:
+    """The sweep plan as a dict: {'eb', 'single', 'sweeps': [{'tb','P','q0','w_store','chunks'}]}.
+    kind: PLAN_EVOLVE (default), PLAN_ADJOINT, or PLAN_TRANSFORM (elem_bytes)."""
+    if kind is None:
+        kind = PLAN_TRANSFORM if state_dtype < 0 else PLAN_EVOLVE
+    need = lib.qaoa_plan_describe(kind, n, state_dtype, elem_bytes, None, 0)
     if need < 0:
         check(-need)
     buf = (ctypes.c_int * need)()
-    lib.qaoa_plan_describe(n, state_dtype, elem_bytes, buf, need)
+    lib.qaoa_plan_describe(kind, n, state_dtype, elem_bytes, buf, need)
     v = list(buf)
     ns, eb, single = v[0], v[1], v[2]
     i = 3
@@ -207,15 +215,27 @@ def qaoa_expectation(n: int, state: torch.Tensor, diag: torch.Tensor, diag_offse
     return out
 
 
+def grad_workspace_bytes(n: int, p: int, state_dtype: int, diag_dtype: int) -> int:
+    out = ctypes.c_size_t(0)
+    check(lib.qaoa_grad_workspace_bytes(n, p, state_dtype, diag_dtype, ctypes.byref(out)))
+    return int(out.value)
+
+
 def qaoa_grad(n: int, gamma, beta, diag: torch.Tensor, state: torch.Tensor, adj: torch.Tensor,
               diag_offset: float = 0.0, out: torch.Tensor | None = None,
               work: torch.Tensor | None = None) -> torch.Tensor:
+    """(E, dE/dgamma[p], dE/dbeta[p]) as a float64[1 + 2p] device tensor.
+    ``state`` and ``adj`` are two scratch states (overwritten)."""
     p = len(gamma)
+    if len(beta) != p:
+        raise ValueError("gamma and beta differ in length")
     sdt, ddt = state_dtype_code(state), diag_dtype_code(diag)
+    if adj.dtype != state.dtype or adj.numel() != state.numel():
+        raise ValueError("adj must match state")
     if out is None:
         out = torch.empty(1 + 2 * p, dtype=torch.float64, device=state.device)
     if work is None:
-        work = alloc_workspace(QAOA_OP_GRAD, n, sdt, ddt, state.device)
+        work = torch.empty(max(16, grad_workspace_bytes(n, p, sdt, ddt)), dtype=torch.uint8, device=state.device)
     check(lib.qaoa_grad(n, p, _f64(gamma), _f64(beta), _dev_ptr(diag), ddt, float(diag_offset), _nbytes(diag),
                         _dev_ptr(state), _dev_ptr(adj), sdt, _nbytes(state), _dev_ptr(out), _dev_ptr(work),
                         _nbytes(work), _stream(state.device)))

@@ -502,8 +502,256 @@ __global__ void __launch_bounds__(512) qaoa_tile_kernel(const SweepArgs a) {
 }
 
 // ----------------------------------------------------------------------------
+// reverse (adjoint) sweeps for the gradient
+// ----------------------------------------------------------------------------
+enum : int { A_FIRST = 1, A_PHASE = 2 };
+
+struct AdjArgs {
+  void* psi;           // forward state, uncomputed in place
+  void* lam;           // adjoint state
+  const void* diag;
+  const double2* ptab; // phase tables, kTabEntries per layer row
+  const double* pset;  // rows (gamma, cos beta, sin beta)
+  double* partials;    // this launch's (beta term, gamma term) per block
+  double diag_offset;
+  int layer;           // row of pset / ptab
+  int nlayers;         // whole-state tile kernel: layers [0, nlayers) in reverse
+  uint64_t layer_partials_stride;  // tile kernel: doubles between layers' partials
+  TileGeom g;
+};
+
+// Im(conj(l0) p1 + conj(l1) p0): the pair's contribution to Im<lambda|X_q|psi>.
+__device__ __forceinline__ double xterm(double pr0, double pi0, double pr1, double pi1, double lr0, double li0,
+                                        double lr1, double li1) {
+  return (lr0 * pi1 - li0 * pr1) + (lr1 * pi0 - li1 * pr0);
+}
+
+// Undo the layer's mixer gates on the tile's active qubits for psi and lambda
+// (gate with -beta), accumulating Im<lambda|X_q|psi> per undone qubit (X_q
+// commutes with every mixer gate, so any point of the undo gives the same value).
+template <class S, int EB>
+__device__ __forceinline__ int undo_mixer(double (&vr)[1 << EB], double (&vi)[1 << EB], double (&lr)[1 << EB],
+                                          double (&li)[1 << EB], typename S::L* lds, const TileGeom& g,
+                                          uint32_t tid, int w, double ca, double sb, double& xacc) {
+  constexpr int E = 1 << EB;
+  for (int ci = 0; ci < g.nchunks; ++ci) {
+    const Chunk ch = g.chunk[ci];
+    if (ch.w != w) {
+      exchange_c<S, EB>(vr, vi, lds, tid, w, ch.w);
+      exchange_c<S, EB>(lr, li, lds, tid, w, ch.w);
+      w = ch.w;
+    }
+#pragma unroll
+    for (int j = 0; j < EB; ++j) {
+      if (j >= ch.jlo && j < ch.jhi) {
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+          if (!(k & (1 << j))) {
+            const int k1 = k | (1 << j);
+            xacc += xterm(vr[k], vi[k], vr[k1], vi[k1], lr[k], li[k], lr[k1], li[k1]);
+            rx_pair(vr[k], vi[k], vr[k1], vi[k1], ca, -sb);
+            rx_pair(lr[k], li[k], lr[k1], li[k1], ca, -sb);
+          }
+        }
+      }
+    }
+  }
+  return w;
+}
+
+// Gamma term Im<lambda|C|psi> of the tile and the phase undo exp(+i g c) on both
+// states; cv holds the stored cost values of the thread's elements.
+template <class D, int EB>
+__device__ __forceinline__ void undo_phase(double (&vr)[1 << EB], double (&vi)[1 << EB], double (&lr)[1 << EB],
+                                           double (&li)[1 << EB], const typename D::RawT (&cv)[1 << EB],
+                                           const AdjArgs& a, const LayerParams& lp, double2* tab, uint32_t tid,
+                                           double& gacc) {
+  constexpr int E = 1 << EB;
+#pragma unroll
+  for (int k = 0; k < E; ++k) gacc += (D::value(cv[k]) + a.diag_offset) * (lr[k] * vi[k] - li[k] * vr[k]);
+  bool fast = false;
+  if constexpr (D::kTable) {
+    int ok = 1;
+    if constexpr (!D::kAlwaysInTable) {
+#pragma unroll
+      for (int k = 0; k < E; ++k) ok &= (D::tab_index(cv[k]) >= 0);
+    }
+    for (uint32_t e = tid; e < (uint32_t)kTabEntries; e += blockDim.x) tab[e] = lp.tab[e];
+    fast = !__syncthreads_or(!ok);
+  }
+  if (fast) {
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int32_t u = D::tab_index(cv[k]);
+      const double2 h = tab[u >> 8], lo = tab[256 + (u & 255)];
+      const double fr = fma(h.x, lo.x, -h.y * lo.y), fi = -fma(h.x, lo.y, h.y * lo.x);  // conjugate
+      cmul_inplace(vr[k], vi[k], fr, fi);
+      cmul_inplace(lr[k], li[k], fr, fi);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const double2 f = phase_direct(lp.g, D::value(cv[k]) + a.diag_offset);
+      cmul_inplace(vr[k], vi[k], f.x, -f.y);
+      cmul_inplace(lr[k], li[k], f.x, -f.y);
+    }
+  }
+}
+
+// One reverse sweep of one layer (multi-tile states):
+//   FIRST  lambda = c * psi from the loaded psi (lambda is only written)
+//   PHASE  after the mixer undo: gamma term and phase undo (first sweep of the layer)
+template <class S, class D, int EB, bool FIRST, bool PHASE>
+__global__ void __launch_bounds__(512) qaoa_adjoint_kernel(const AdjArgs a) {
+  constexpr int E = 1 << EB;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  typename S::L* lds = reinterpret_cast<typename S::L*>(smem_raw);
+  double2* tab = reinterpret_cast<double2*>(smem_raw + (1u << a.g.tb) * S::kBytes);
+  const uint32_t tid = threadIdx.x;
+  const int P = a.g.P, q0 = a.g.q0;
+  const uint64_t base = block_base(blockIdx.x, a.g.tb, P, q0);
+  const size_t r = (size_t)a.layer;
+  const LayerParams lp{a.pset[3 * r], a.pset[3 * r + 1], a.pset[3 * r + 2], a.ptab + r * kTabEntries};
+  const int w_load = a.g.tb - EB;
+  int w = w_load;
+  double vr[E], vi[E], lr[E], li[E];
+  typename D::RawT cv[(FIRST || PHASE) ? E : 1];
+  {
+    const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), P, q0);
+#pragma unroll
+    for (int k = 0; k < E; ++k) S::load(a.psi, xb + tile_off((uint32_t)k << w, P, q0), vr[k], vi[k]);
+    if constexpr (FIRST || PHASE) {
+#pragma unroll
+      for (int k = 0; k < E; ++k) cv[k] = D::load_raw(a.diag, xb + tile_off((uint32_t)k << w, P, q0));
+    }
+    if constexpr (FIRST) {
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const double c = D::value(cv[k]) + a.diag_offset;
+        lr[k] = c * vr[k];
+        li[k] = c * vi[k];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < E; ++k) S::load(a.lam, xb + tile_off((uint32_t)k << w, P, q0), lr[k], li[k]);
+    }
+  }
+  double xacc = 0.0, gacc = 0.0;
+  w = undo_mixer<S, EB>(vr, vi, lr, li, lds, a.g, tid, w, lp.ca, lp.sb, xacc);
+  const int w_out = PHASE ? w_load : a.g.w_store;
+  if (w != w_out) {
+    exchange_c<S, EB>(vr, vi, lds, tid, w, w_out);
+    exchange_c<S, EB>(lr, li, lds, tid, w, w_out);
+    w = w_out;
+  }
+  if constexpr (PHASE) undo_phase<D, EB>(vr, vi, lr, li, cv, a, lp, tab, tid, gacc);
+  {
+    const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), P, q0);
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const uint64_t x = xb + tile_off((uint32_t)k << w, P, q0);
+      S::store(a.psi, x, vr[k], vi[k]);
+      S::store(a.lam, x, lr[k], li[k]);
+    }
+  }
+  __syncthreads();  // the tables and tile buffer are reused as reduction scratch
+  block_sum2(xacc, gacc, reinterpret_cast<double*>(smem_raw));
+  if (tid == 0) {
+    a.partials[2 * (uint64_t)blockIdx.x] = xacc;
+    a.partials[2 * (uint64_t)blockIdx.x + 1] = gacc;
+  }
+}
+
+// Whole state in one tile: lambda = c psi, then layers nlayers-1 .. 0 in reverse;
+// layer l's (beta term, gamma term) go to partials + l * layer_partials_stride.
+template <class S, class D, int EB>
+__global__ void __launch_bounds__(512) qaoa_adjoint_tile_kernel(const AdjArgs a) {
+  constexpr int E = 1 << EB;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  typename S::L* lds = reinterpret_cast<typename S::L*>(smem_raw);
+  double2* tab = reinterpret_cast<double2*>(smem_raw + (1u << a.g.tb) * S::kBytes);
+  double* scratch = reinterpret_cast<double*>(smem_raw + (1u << a.g.tb) * S::kBytes + kTabEntries * sizeof(double2));
+  const uint32_t tid = threadIdx.x;
+  const int w_load = a.g.tb - EB;
+  int w = w_load;
+  double vr[E], vi[E], lr[E], li[E];
+  typename D::RawT cv[E];
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const uint32_t x = tmap<EB>(tid, k, w);
+    S::load(a.psi, x, vr[k], vi[k]);
+    cv[k] = D::load_raw(a.diag, x);
+    const double c = D::value(cv[k]) + a.diag_offset;
+    lr[k] = c * vr[k];
+    li[k] = c * vi[k];
+  }
+  for (int l = a.nlayers - 1; l >= 0; --l) {
+    const LayerParams lp{a.pset[3 * l], a.pset[3 * l + 1], a.pset[3 * l + 2], a.ptab + (size_t)l * kTabEntries};
+    double xacc = 0.0, gacc = 0.0;
+    w = undo_mixer<S, EB>(vr, vi, lr, li, lds, a.g, tid, w, lp.ca, lp.sb, xacc);
+    if (w != w_load) {
+      exchange_c<S, EB>(vr, vi, lds, tid, w, w_load);
+      exchange_c<S, EB>(lr, li, lds, tid, w, w_load);
+      w = w_load;
+    }
+    __syncthreads();  // previous layer's table reads are done
+    undo_phase<D, EB>(vr, vi, lr, li, cv, a, lp, tab, tid, gacc);
+    block_sum2(xacc, gacc, scratch);
+    if (tid == 0) {
+      a.partials[(uint64_t)l * a.layer_partials_stride] = xacc;
+      a.partials[(uint64_t)l * a.layer_partials_stride + 1] = gacc;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const uint32_t x = tmap<EB>(tid, k, w);
+    S::store(a.psi, x, vr[k], vi[k]);
+    S::store(a.lam, x, lr[k], li[k]);
+  }
+}
+
+// out[1 + l] = 2 * sum of layer l's gamma terms, out[1 + p + l] = 2 * sum of its
+// beta terms; layer l's partials: nsw runs of `blocks` pairs at
+// partials + l * layer_stride + s * blocks * 2 (the gamma term only in run 0).
+__global__ void __launch_bounds__(256) grad_finalize_kernel(const double* partials, int p, int nsw, uint64_t blocks,
+                                                            uint64_t layer_stride, double* out) {
+  __shared__ double scratch[16];
+  const int l = blockIdx.x;
+  const double* part = partials + (uint64_t)l * layer_stride;
+  double xb = 0.0, gg = 0.0;
+  for (int s = 0; s < nsw; ++s)
+    for (uint64_t i = threadIdx.x; i < blocks; i += blockDim.x) {
+      xb += part[2 * (s * blocks + i)];
+      if (s == 0) gg += part[2 * i + 1];
+    }
+  block_sum2(xb, gg, scratch);
+  if (threadIdx.x == 0) {
+    out[1 + l] = 2.0 * gg;
+    out[1 + p + l] = 2.0 * xb;
+  }
+}
+
+// ----------------------------------------------------------------------------
 // batched evaluation helpers
 // ----------------------------------------------------------------------------
+
+// Stage 1 of the two-stage reduction of per-workgroup partials: block b of
+// state s (blockIdx.y) sums pairs [b * per, min((b + 1) * per, count)) of that
+// state's partials and writes tmp[s * tstride + 2 b + {0,1}].  Fixed order.
+__global__ void __launch_bounds__(256) reduce_chunks_kernel(const double* partials, uint64_t count, uint64_t stride,
+                                                            uint64_t per, double* tmp, uint64_t tstride) {
+  __shared__ double scratch[16];
+  const double* part = partials + (uint64_t)blockIdx.y * stride;
+  const uint64_t lo = (uint64_t)blockIdx.x * per;
+  const uint64_t hi = lo + per < count ? lo + per : count;
+  double e = 0.0, q = 0.0;
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) { e += part[2 * i]; q += part[2 * i + 1]; }
+  block_sum2(e, q, scratch);
+  if (threadIdx.x == 0) {
+    tmp[(uint64_t)blockIdx.y * tstride + 2 * blockIdx.x] = e;
+    tmp[(uint64_t)blockIdx.y * tstride + 2 * blockIdx.x + 1] = q;
+  }
+}
 
 // out[2 s + {0,1}] = fixed-order sum of set s's `count` partial pairs.
 __global__ void __launch_bounds__(256) finalize_batch_kernel(const double* partials, uint64_t count,

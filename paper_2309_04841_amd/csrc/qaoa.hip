@@ -51,10 +51,10 @@ bool valid_diag_dtype(int dt) { return dt == QAOA_DIAG_F64 || dt == QAOA_DIAG_I3
 
 // Largest tile (log2 elements) per dtype: 64 KiB of LDS per workgroup, so two
 // workgroups fit in a CU's 160 KiB and overlap memory with exchanges.
-// Capped at 13 bits so a tile never needs more than 512 threads (2^(13-kEB)).
-int tile_bits_for_bytes(size_t elem_bytes) {
+// Capped so a tile never needs more than 512 threads (2^(cap - eb)).
+int tile_bits_for_bytes(size_t elem_bytes, int cap) {
   int tb = 0;
-  while (tb < 13 && ((size_t)1 << (tb + 1)) * elem_bytes <= 65536) ++tb;
+  while (tb < cap && ((size_t)1 << (tb + 1)) * elem_bytes <= 65536) ++tb;
   return tb;
 }
 // Minimum passenger bits so that a high sweep touches >= 128 contiguous bytes.
@@ -95,33 +95,37 @@ struct Plan {
   std::vector<qk::TileGeom> sweeps;
 };
 
-Plan make_plan(int n, size_t elem_bytes) {
+Plan make_plan(int n, size_t elem_bytes, int eb = kEB) {
   Plan pl;
-  const int tbmax = tile_bits_for_bytes(elem_bytes);
+  const int tbmax = tile_bits_for_bytes(elem_bytes, 9 + eb);
   const int pmin = min_passenger_bits(elem_bytes);
   const int smin = pmin;  // store runs of >= 128 B
   if (n <= tbmax) {
     pl.single = true;
-    pl.eb = std::min(kEB, n);
+    pl.eb = std::min(eb, n);
     pl.sweeps.push_back(make_geom(n, 0, 0, pl.eb, true, 0));
     return pl;
   }
   pl.single = false;
-  pl.eb = kEB;
-  pl.sweeps.push_back(make_geom(tbmax, 0, 0, kEB, true, smin));
+  pl.eb = eb;
+  pl.sweeps.push_back(make_geom(tbmax, 0, 0, eb, true, smin));
   const int r = n - tbmax;
   const int hmax = tbmax - pmin;
   const int ns = (r + hmax - 1) / hmax;
   int q = tbmax;
   for (int i = 0; i < ns; ++i) {
     const int h = r / ns + (i < r % ns ? 1 : 0);
-    pl.sweeps.push_back(make_geom(tbmax, tbmax - h, q, kEB, false, smin));
+    pl.sweeps.push_back(make_geom(tbmax, tbmax - h, q, eb, false, smin));
     q += h;
   }
   return pl;
 }
 
 uint64_t plan_blocks(int n, const qk::TileGeom& g) { return (uint64_t)1 << (n - g.tb); }
+
+// Reverse (adjoint) sweeps hold two states per thread: 8 elements of each.
+constexpr int kEBAdj = 3;
+Plan adjoint_plan(int n, size_t state_bytes) { return make_plan(n, state_bytes, kEBAdj); }
 
 // ---------------------------------------------------------------------------
 // typed launchers
@@ -209,6 +213,64 @@ void launch_tile_s(const qk::SweepArgs& a, int diag_dtype, int eb, uint32_t sets
 void launch_tile(const qk::SweepArgs& a, int state_dtype, int diag_dtype, int eb, uint32_t sets, hipStream_t st) {
   if (state_dtype == QAOA_C128) launch_tile_s<qk::C128>(a, diag_dtype, eb, sets, st);
   else launch_tile_s<qk::C64>(a, diag_dtype, eb, sets, st);
+}
+
+template <class S, class D, bool FIRST, bool PHASE>
+void launch_adj_f(const qk::AdjArgs& a, uint64_t blocks, hipStream_t st) {
+  const uint32_t threads = 1u << (a.g.tb - kEBAdj);
+  const size_t tile = ((size_t)1 << a.g.tb) * S::kBytes;
+  const size_t lds = std::max<size_t>(tile + qk::kTabEntries * sizeof(double2), std::max<size_t>(16, 2 * threads) * sizeof(double));
+  hipLaunchKernelGGL((qk::qaoa_adjoint_kernel<S, D, kEBAdj, FIRST, PHASE>), dim3((uint32_t)blocks), dim3(threads), lds,
+                     st, a);
+}
+
+template <class S, class D>
+int launch_adj_d(const qk::AdjArgs& a, bool first, bool phase, uint64_t blocks, hipStream_t st) {
+  if (first && !phase) launch_adj_f<S, D, true, false>(a, blocks, st);
+  else if (!first && phase) launch_adj_f<S, D, false, true>(a, blocks, st);
+  else if (!first && !phase) launch_adj_f<S, D, false, false>(a, blocks, st);
+  else return fail(QAOA_ERR_UNSUPPORTED, "internal: adjoint flag combination not instantiated");
+  return QAOA_OK;
+}
+
+template <class S, class D, int EB>
+void launch_adj_tile_t(const qk::AdjArgs& a, hipStream_t st) {
+  const uint32_t threads = 1u << (a.g.tb - EB);
+  const size_t lds = ((size_t)1 << a.g.tb) * S::kBytes + qk::kTabEntries * sizeof(double2) +
+                     std::max<size_t>(16, 2 * threads) * sizeof(double);
+  hipLaunchKernelGGL((qk::qaoa_adjoint_tile_kernel<S, D, EB>), dim3(1), dim3(threads), lds, st, a);
+}
+
+template <class S, class D>
+void launch_adj_tile_d(const qk::AdjArgs& a, int eb, hipStream_t st) {
+  switch (eb) {
+    case 1: launch_adj_tile_t<S, D, 1>(a, st); break;
+    case 2: launch_adj_tile_t<S, D, 2>(a, st); break;
+    default: launch_adj_tile_t<S, D, 3>(a, st); break;
+  }
+}
+
+// Reverse sweep (tile == false) or whole-state reverse pass (tile == true).
+template <class S>
+int launch_adj_s(const qk::AdjArgs& a, int ddt, bool tile, int eb, bool first, bool phase, uint64_t blocks,
+                 hipStream_t st) {
+  switch (ddt) {
+    case QAOA_DIAG_I32:
+      if (tile) { launch_adj_tile_d<S, qk::DI32>(a, eb, st); return QAOA_OK; }
+      return launch_adj_d<S, qk::DI32>(a, first, phase, blocks, st);
+    case QAOA_DIAG_U16:
+      if (tile) { launch_adj_tile_d<S, qk::DU16>(a, eb, st); return QAOA_OK; }
+      return launch_adj_d<S, qk::DU16>(a, first, phase, blocks, st);
+    default:
+      if (tile) { launch_adj_tile_d<S, qk::DF64>(a, eb, st); return QAOA_OK; }
+      return launch_adj_d<S, qk::DF64>(a, first, phase, blocks, st);
+  }
+}
+
+int launch_adj(const qk::AdjArgs& a, int sdt, int ddt, bool tile, int eb, bool first, bool phase, uint64_t blocks,
+               hipStream_t st) {
+  if (sdt == QAOA_C128) return launch_adj_s<qk::C128>(a, ddt, tile, eb, first, phase, blocks, st);
+  return launch_adj_s<qk::C64>(a, ddt, tile, eb, first, phase, blocks, st);
 }
 
 template <class S, class D>
@@ -312,9 +374,11 @@ constexpr size_t kStatWork = (3 * kStatBlocks + 4) * sizeof(int64_t);
 // [parameter rows: 3 doubles each][phase tables: kTabEntries double2 per row].
 // A single evaluation with host angles uses kMaxLayersPerLaunch rows (one
 // chunk of layers at a time); a batch with device angles uses batch * p rows.
+constexpr uint64_t kReduceChunks = 1024;  // stage-1 chunks of the two-stage reduction
+
 struct EvolveWork {
   size_t partials_stride;  // doubles per state
-  size_t partials_bytes, pset_bytes, tab_bytes, total;
+  size_t partials_bytes, pset_bytes, tab_bytes, tmp_bytes, total;
 };
 EvolveWork evolve_work(int n, size_t states, size_t rows, int state_dtype) {
   EvolveWork b{};
@@ -324,11 +388,51 @@ EvolveWork evolve_work(int n, size_t states, size_t rows, int state_dtype) {
   b.partials_bytes = sizeof(double) * b.partials_stride * states;
   b.pset_bytes = ((3 * sizeof(double) * rows + 255) / 256) * 256;
   b.tab_bytes = rows * qk::kTabEntries * sizeof(double2);
-  b.total = b.partials_bytes + b.pset_bytes + b.tab_bytes;
+  b.tmp_bytes = sizeof(double) * 2 * kReduceChunks * states;
+  b.total = b.partials_bytes + b.pset_bytes + b.tab_bytes + b.tmp_bytes;
   return b;
+}
+
+// (E, norm) of `sets` states from `count` partial pairs each (stride doubles
+// apart) into out[2 s + {0,1}]: two fixed-order stages through tmp.
+int enqueue_reduce(const double* partials, uint64_t count, uint64_t stride, uint32_t sets, double* tmp, double* out,
+                   hipStream_t st) {
+  if (count <= 256) {
+    hipLaunchKernelGGL(qk::finalize_batch_kernel, dim3(sets), dim3(256), 0, st, partials, count, stride, out);
+    LAUNCH_CHECK("finalize_batch_kernel");
+    return QAOA_OK;
+  }
+  const uint64_t chunks = std::min<uint64_t>(kReduceChunks, (count + 255) / 256);
+  const uint64_t per = (count + chunks - 1) / chunks;
+  const uint64_t nchunks = (count + per - 1) / per;
+  hipLaunchKernelGGL(qk::reduce_chunks_kernel, dim3((uint32_t)nchunks, sets), dim3(256), 0, st, partials, count,
+                     stride, per, tmp, (uint64_t)(2 * kReduceChunks));
+  LAUNCH_CHECK("reduce_chunks_kernel");
+  hipLaunchKernelGGL(qk::finalize_batch_kernel, dim3(sets), dim3(256), 0, st, (const double*)tmp, nchunks,
+                     (uint64_t)(2 * kReduceChunks), out);
+  LAUNCH_CHECK("finalize_batch_kernel");
+  return QAOA_OK;
 }
 size_t evolve_work_bytes(int n, int state_dtype) { return evolve_work(n, 1, qk::kMaxLayersPerLaunch, state_dtype).total; }
 size_t partials_bytes(int n, int state_dtype) { return evolve_work(n, 1, 0, state_dtype).partials_bytes; }
+
+// Gradient workspace: [forward evolve workspace][p parameter rows][p table rows]
+// [reverse partials: p layers x sweeps x blocks x 2 doubles].
+struct GradWork {
+  size_t fwd, pset_off, tab_off, rev_off, layer_stride /* doubles */, total;
+};
+GradWork grad_work(int n, int p, int state_dtype) {
+  GradWork g{};
+  const Plan pl = adjoint_plan(n, state_elem_bytes(state_dtype));
+  const uint64_t blocks = pl.single ? 1 : plan_blocks(n, pl.sweeps[0]);
+  g.fwd = evolve_work_bytes(n, state_dtype);
+  g.pset_off = g.fwd;
+  g.tab_off = g.pset_off + ((3 * sizeof(double) * (size_t)p + 255) / 256) * 256;
+  g.rev_off = g.tab_off + (size_t)p * qk::kTabEntries * sizeof(double2);
+  g.layer_stride = 2 * pl.sweeps.size() * blocks;
+  g.total = g.rev_off + sizeof(double) * g.layer_stride * (size_t)p;
+  return g;
+}
 
 double table_base(int diag_dtype, double diag_offset) {
   return (diag_dtype == QAOA_DIAG_I32 ? qk::DI32::kTableBase : qk::DU16::kTableBase) + diag_offset;
@@ -632,9 +736,10 @@ static int enqueue_evolve(int n, int p, int batch, const double* h_gamma, const 
       }
     }
     if (d_out) {
-      hipLaunchKernelGGL(qk::finalize_batch_kernel, dim3(sets), dim3(256), 0, st, (const double*)a.partials,
-                         last_blocks, (uint64_t)ew.partials_stride, d_out + 2 * (size_t)s0);
-      LAUNCH_CHECK("finalize_batch_kernel");
+      double* tmp = reinterpret_cast<double*>(wk + ew.partials_bytes + ew.pset_bytes + ew.tab_bytes) +
+                    2 * kReduceChunks * (size_t)s0;
+      rc = enqueue_reduce(a.partials, last_blocks, ew.partials_stride, sets, tmp, d_out + 2 * (size_t)s0, st);
+      if (rc) return rc;
     }
   }
   return QAOA_OK;
@@ -739,17 +844,18 @@ int qaoa_evolve_batch(int n, int p, int batch, const double* d_gamma, const doub
                         state_dtype, init, d_out, G, d_work, st);
 }
 
-int qaoa_plan_describe(int n, int state_dtype, int elem_bytes, int* out, int cap) {
+int qaoa_plan_describe(int kind, int n, int state_dtype, int elem_bytes, int* out, int cap) {
   if (n < 1 || n > QAOA_MAX_QUBITS) return -fail(QAOA_ERR_INVALID, "n=%d out of range", n);
-  size_t eb_bytes;
-  if (state_dtype >= 0) {
+  Plan pl;
+  if (kind == 0 || kind == 1) {
     if (!valid_state_dtype(state_dtype)) return -fail(QAOA_ERR_INVALID, "bad state dtype %d", state_dtype);
-    eb_bytes = state_elem_bytes(state_dtype);
-  } else {
+    pl = kind == 0 ? make_plan(n, state_elem_bytes(state_dtype)) : adjoint_plan(n, state_elem_bytes(state_dtype));
+  } else if (kind == 2) {
     if (elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8) return -fail(QAOA_ERR_INVALID, "bad elem_bytes");
-    eb_bytes = (size_t)elem_bytes;
+    pl = make_plan(n, (size_t)elem_bytes);
+  } else {
+    return -fail(QAOA_ERR_INVALID, "bad plan kind %d", kind);
   }
-  const Plan pl = make_plan(n, eb_bytes);
   std::vector<int> v;
   v.push_back((int)pl.sweeps.size());
   v.push_back(pl.eb);
@@ -762,6 +868,16 @@ int qaoa_plan_describe(int n, int state_dtype, int elem_bytes, int* out, int cap
   return (int)v.size();
 }
 
+int qaoa_grad_workspace_bytes(int n, int p, int state_dtype, int diag_dtype, size_t* bytes) {
+  if (!bytes) return fail(QAOA_ERR_INVALID, "bytes is NULL");
+  if (n < 1 || n > QAOA_MAX_QUBITS) return fail(QAOA_ERR_INVALID, "n=%d out of range [1, %d]", n, QAOA_MAX_QUBITS);
+  if (p < 1) return fail(QAOA_ERR_INVALID, "p must be >= 1");
+  if (!valid_state_dtype(state_dtype)) return fail(QAOA_ERR_INVALID, "bad state dtype %d", state_dtype);
+  if (!valid_diag_dtype(diag_dtype)) return fail(QAOA_ERR_INVALID, "bad diag dtype %d", diag_dtype);
+  *bytes = grad_work(n, p, state_dtype).total;
+  return QAOA_OK;
+}
+
 int qaoa_grad(int n, int p, const double* gamma, const double* beta, const void* d_diag, int diag_dtype,
               double diag_offset, size_t diag_bytes, void* d_state, void* d_adj, int state_dtype,
               size_t state_bytes, double* d_out, void* d_work, size_t work_bytes, void* stream) {
@@ -769,9 +885,73 @@ int qaoa_grad(int n, int p, const double* gamma, const double* beta, const void*
   if (rc) return rc;
   rc = validate_angles(p, gamma, beta);
   if (rc) return rc;
+  if (p < 1) return fail(QAOA_ERR_INVALID, "p must be >= 1 for a gradient");
   if (!d_adj || !d_out) return fail(QAOA_ERR_INVALID, "d_adj/d_out is NULL");
-  (void)d_work; (void)work_bytes; (void)stream;
-  return fail(QAOA_ERR_UNSUPPORTED, "qaoa_grad is not implemented in this build");
+  if (d_adj == d_state) return fail(QAOA_ERR_INVALID, "d_adj must not alias d_state");
+  const GradWork gw = grad_work(n, p, state_dtype);
+  if (!d_work || work_bytes < gw.total) return fail(QAOA_ERR_NOMEM, "workspace too small: need %zu bytes", gw.total);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* wk = reinterpret_cast<char*>(d_work);
+
+  // forward pass: psi_p in d_state, (E, norm) in d_out[0..1] (d_out[1] is
+  // overwritten by the gradient below)
+  rc = enqueue_evolve(n, p, 1, gamma, beta, nullptr, nullptr, d_diag, diag_dtype, diag_offset, d_state, state_dtype, 1,
+                      d_out, 1, d_work, st);
+  if (rc) return rc;
+
+  // parameter rows and tables of all p layers
+  double* pset = reinterpret_cast<double*>(wk + gw.pset_off);
+  double2* tab = reinterpret_cast<double2*>(wk + gw.tab_off);
+  double* rev = reinterpret_cast<double*>(wk + gw.rev_off);
+  const bool use_tab = diag_dtype != QAOA_DIAG_F64;
+  for (int l0 = 0; l0 < p; l0 += 32) {
+    qk::PrepArgs pa{};
+    pa.pset = pset + 3 * (size_t)l0;
+    pa.tab = use_tab ? tab + (size_t)l0 * qk::kTabEntries : nullptr;
+    pa.base = use_tab ? table_base(diag_dtype, diag_offset) : 0.0;
+    pa.rows = std::min(32, p - l0);
+    for (int i = 0; i < pa.rows; ++i) { pa.gamma[i] = gamma[l0 + i]; pa.beta[i] = beta[l0 + i]; }
+    hipLaunchKernelGGL(qk::layer_prep_kernel, dim3(pa.rows), dim3(256), 0, st, pa);
+    LAUNCH_CHECK("layer_prep_kernel");
+  }
+
+  const Plan pl = adjoint_plan(n, state_elem_bytes(state_dtype));
+  qk::AdjArgs a{};
+  a.psi = d_state;
+  a.lam = d_adj;
+  a.diag = d_diag;
+  a.diag_offset = diag_offset;
+  a.pset = pset;
+  a.ptab = tab;
+  const int nsw = (int)pl.sweeps.size();
+  uint64_t blocks = 1;
+  if (pl.single) {
+    a.g = pl.sweeps[0];
+    a.nlayers = p;
+    a.partials = rev;
+    a.layer_partials_stride = gw.layer_stride;
+    rc = launch_adj(a, state_dtype, diag_dtype, true, pl.eb, true, true, 1, st);
+    if (rc) return rc;
+    LAUNCH_CHECK("qaoa_adjoint_tile_kernel");
+  } else {
+    blocks = plan_blocks(n, pl.sweeps[0]);
+    for (int l = p - 1; l >= 0; --l) {
+      a.layer = l;
+      for (int sw = nsw - 1; sw >= 0; --sw) {
+        a.g = pl.sweeps[sw];
+        a.partials = rev + (size_t)l * gw.layer_stride + (size_t)sw * blocks * 2;
+        const bool first = (l == p - 1) && (sw == nsw - 1);
+        rc = launch_adj(a, state_dtype, diag_dtype, false, kEBAdj, first, sw == 0, blocks, st);
+        if (rc) return rc;
+        LAUNCH_CHECK("qaoa_adjoint_kernel");
+      }
+    }
+  }
+  hipLaunchKernelGGL(qk::grad_finalize_kernel, dim3(p), dim3(256), 0, st, (const double*)rev, p, nsw, blocks,
+                     (uint64_t)gw.layer_stride, d_out);
+  LAUNCH_CHECK("grad_finalize_kernel");
+  (void)work_bytes;
+  return QAOA_OK;
 }
 
 }  // extern "C"

@@ -77,6 +77,19 @@ class Simulator:
         out = _lib.qaoa_expectation(self.n, result, self.diag, self.offset, out=self._out, work=self._work)
         return float(out[1].item())
 
+    def get_gradient(self, gamma, beta):
+        """(E, dE/dgamma, dE/dbeta) from |+>^n by the adjoint method on the GPU."""
+        gamma = np.atleast_1d(np.asarray(gamma, dtype=np.float64))
+        beta = np.atleast_1d(np.asarray(beta, dtype=np.float64))
+        p = len(gamma)
+        if getattr(self, "_grad_bufs", None) is None:
+            self._grad_bufs = tuple(torch.empty(1 << self.n, dtype=self.state_dtype, device=self.device)
+                                    for _ in range(2))
+        psi, adj = self._grad_bufs
+        out = _lib.qaoa_grad(self.n, gamma, beta, self.diag, psi, adj, diag_offset=self.offset)
+        o = out.cpu().numpy()
+        return float(o[0]), o[1:1 + p].copy(), o[1 + p:].copy()
+
     def get_statevector(self, result: torch.Tensor) -> np.ndarray:
         return result.cpu().numpy()
 

@@ -41,7 +41,8 @@ def test_version_and_last_error():
 
 def test_workspace_bytes():
     # per-block (E, norm) partials of the last sweep + parameter rows and phase tables of 32 layers
-    assert _lib.workspace_bytes(_lib.QAOA_OP_EVOLVE, 26, _lib.QAOA_C128) == 16 * (1 << 14) + 3 * 8 * 32 + 32 * 512 * 16
+    # + the first stage of the two-stage reduction
+    assert _lib.workspace_bytes(_lib.QAOA_OP_EVOLVE, 26, _lib.QAOA_C128) == 16 * (1 << 14) + 3 * 8 * 32 + 32 * 512 * 16 + 16 * 1024
     assert _lib.workspace_bytes(_lib.QAOA_OP_PRECOMPUTE, 20, diag_dtype=_lib.QAOA_DIAG_F64) == 0
     assert _lib.workspace_bytes(_lib.QAOA_OP_PRECOMPUTE, 20, diag_dtype=_lib.QAOA_DIAG_U16) >= 4 << 20
     with pytest.raises(_lib.QaoaError):
@@ -122,13 +123,19 @@ def test_precompute_rejects(kw, code):
     assert _precompute(**kw) == code
 
 
-def test_grad_validates_then_unsupported():
+def test_grad_validates():
     N = 1 << 8
     g = (ctypes.c_double * 1)(0.1)
+    # no adjoint buffer, aliasing buffers, p = 0, missing workspace
     assert _lib.lib.qaoa_grad(8, 1, g, g, FAKE, 1, 0.0, 4 * N, FAKE, None, 1, 16 * N, FAKE, None, 0, None) \
         == _lib.QAOA_ERR_INVALID
     assert _lib.lib.qaoa_grad(8, 1, g, g, FAKE, 1, 0.0, 4 * N, FAKE, FAKE, 1, 16 * N, FAKE, None, 0, None) \
-        == _lib.QAOA_ERR_UNSUPPORTED
+        == _lib.QAOA_ERR_INVALID
+    other = ctypes.c_void_p(0x2000)
+    assert _lib.lib.qaoa_grad(8, 0, g, g, FAKE, 1, 0.0, 4 * N, FAKE, other, 1, 16 * N, FAKE, None, 0, None) \
+        == _lib.QAOA_ERR_INVALID
+    assert _lib.lib.qaoa_grad(8, 1, g, g, FAKE, 1, 0.0, 4 * N, FAKE, other, 1, 16 * N, FAKE, None, 0, None) \
+        == _lib.QAOA_ERR_NOMEM
 
 
 # ---------------------------------------------------------------------------
@@ -227,6 +234,14 @@ def test_state_plans(sdt, eb):
 def test_transform_plans(elem):
     for n in range(1, _lib.QAOA_MAX_QUBITS + 1):
         _check_plan(n, _lib.plan_describe(n, -1, elem), elem, emulate=n <= 16)
+
+
+@pytest.mark.parametrize("sdt,eb", [(_lib.QAOA_C128, 16), (_lib.QAOA_C64, 8)])
+def test_adjoint_plans(sdt, eb):
+    for n in range(1, _lib.QAOA_MAX_QUBITS + 1):
+        plan = _lib.plan_describe(n, sdt, kind=_lib.PLAN_ADJOINT)
+        assert plan["eb"] <= 3
+        _check_plan(n, plan, eb, emulate=n <= 16)
 
 
 def test_headline_plans_sweep_counts():

@@ -13,6 +13,7 @@ import pytest
 import oracle
 import test_oracle_diag as D
 import test_oracle_evolve as V
+import test_oracle_grad as G
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
 
@@ -33,6 +34,13 @@ MUTANTS = {
         "oracle_apply_phase(n, c, gamma[l], psi);\n        oracle_apply_mixer(n, beta[l], psi);",
         "oracle_apply_mixer(n, beta[l], psi);\n        oracle_apply_phase(n, c, gamma[l], psi);"),
     "plus_state_unnormalised": ("const double a = pow(2.0, -0.5 * n);", "const double a = pow(2.0, -0.5 * (n - 1));"),
+    # adjoint: gamma term taken before the mixer is undone
+    "grad_gamma_before_mixer_undo": (
+        "        out[1 + p + l] = 2.0 * sb;\n        oracle_apply_mixer(n, -beta[l], psi);\n        oracle_apply_mixer(n, -beta[l], lam);\n        double sg = 0.0;",
+        "        out[1 + p + l] = 2.0 * sb;\n        double sg = 0.0;"),
+    # adjoint: conjugation on the wrong factor (sign of the beta term)
+    "grad_beta_conjugate": ("sq += lam[2 * x] * psi[2 * y + 1] - lam[2 * x + 1] * psi[2 * y];",
+                            "sq += lam[2 * x + 1] * psi[2 * y] - lam[2 * x] * psi[2 * y + 1];"),
 }
 
 PINS = [
@@ -45,6 +53,8 @@ PINS = [
     lambda: V.test_evolve_matches_dense_expm("labs", 6, 2),
     lambda: V.test_p1_maxcut_closed_form(V._k4),
     lambda: V.test_norm_preserved_and_beta_zero_mean(4),
+    lambda: G.test_grad_matches_central_differences(5, 3, 1),
+    G.test_p1_maxcut_gradient_closed_form,
 ]
 
 
