@@ -84,12 +84,134 @@ def cpu_baseline(cfg, budget_s=20.0):
                        f"like the GPU precompute")
 
 
+def bench_batch(args):
+    """Batched parameter sweep: weighted MaxCut G(22, 0.3), p=6, 512 (gamma, beta)
+    sets, complex64, one qaoa_evolve_batch call (graph-replayable) vs a loop of
+    single qaoa_evolve calls on the same GPU."""
+    import numpy as np
+    import torch
+
+    import paper_2309_04841_amd as q
+    from paper_2309_04841_amd import _lib, tune
+    import workloads as W
+    cfg = W.C3()
+    n, p = cfg["n"], cfg["p"]
+    gam, bet = cfg["gamma"], cfg["beta"]
+    batch = gam.shape[0]
+    dev = torch.device("cuda:0")
+    diag, off = q.qaoa_precompute_diag(n, cfg["terms"], "i32", device=dev)
+    dg, db = torch.from_numpy(gam).to(dev), torch.from_numpy(bet).to(dev)
+    states = torch.empty(batch, 1 << n, dtype=torch.complex64, device=dev)
+    out = torch.empty(batch, 2, dtype=torch.float64, device=dev)
+    spp = args.sets_per_pass or tune.best_sets_per_pass(n, p, batch, diag, off, states, out, dg, db)
+    work = torch.empty(_lib.batch_workspace_bytes(n, p, batch, _lib.QAOA_C64, _lib.QAOA_DIAG_I32), dtype=torch.uint8,
+                       device=dev)
+
+    def run_batch():
+        _lib.qaoa_evolve_batch(n, dg, db, diag, states, diag_offset=off, out=out, sets_per_pass=spp, work=work)
+
+    for _ in range(args.warmup):
+        run_batch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run_batch()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+    # plain single-evaluation path, same kernels, one state at a time
+    psi = torch.empty(1 << n, dtype=torch.complex64, device=dev)
+    o1 = torch.empty(2, dtype=torch.float64, device=dev)
+    w1 = _lib.alloc_workspace(_lib.QAOA_OP_EVOLVE, n, _lib.QAOA_C64, _lib.QAOA_DIAG_I32, dev)
+    for s in range(4):
+        q.qaoa_evolve(n, gam[s], bet[s], diag, psi, diag_offset=off, out=o1, work=w1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(batch):
+        q.qaoa_evolve(n, gam[s], bet[s], diag, psi, diag_offset=off, out=o1, work=w1)
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    N = 1 << n
+    bytes_per_set = (p * (2 * 2 * 8 + 4) + 4 - 8) * N  # 2 sweeps per layer at n=22 complex64
+    return {"metric": "batched QAOA evals/s, weighted MaxCut G(22,0.3) p=6, 512 sets", "value": batch / t_batch,
+            "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": 1e3 * t_batch, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": cfg["name"], "n": n, "p": p, "sets": batch, "state": "complex64",
+                       "sets_per_pass": spp},
+            "single_path_evals_per_s": batch / t_single, "speedup_vs_single": t_single / t_batch,
+            "effective_GBps": bytes_per_set * batch / t_batch / 1e9}
+
+
+def bench_serve(args):
+    """Served mix: Poisson arrivals at --rate, 60% objective / 40% gradient,
+    LABS or 3-regular MaxCut with n ~ U{16..30}, p ~ U{1..20}, complex64;
+    p50/p99 latency and requests/s, vs the same requests run one at a time."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import paper_2309_04841_amd as q
+    import workloads as W
+    rng = np.random.default_rng(7)
+    ns = list(range(16, 31))
+    srv = q.QAOAServer(arena_bytes=160 << 30, num_streams=4, max_in_flight=16)
+    probs = {}
+    for n in ns:
+        probs[("labs", n)] = (n, W.labs_terms(n))
+        probs[("maxcut", n)] = (n, W.maxcut_terms(W.random_regular_graph(3, n, seed=100 + n)))
+    pids = {k: srv.add_problem(n, terms) for k, (n, terms) in probs.items()}
+    keys = list(probs)
+    reqs = []
+    for _ in range(args.requests):
+        k = keys[int(rng.integers(0, len(keys)))]
+        p = int(rng.integers(1, 21))
+        reqs.append((k, rng.uniform(0, 1, size=p), rng.uniform(0, np.pi, size=p), bool(rng.random() < 0.4)))
+    arrivals = np.cumsum(rng.exponential(1.0 / args.rate, size=len(reqs)))
+    tickets = []
+
+    def submitter():
+        t0 = time.perf_counter()
+        for (k, g, b, grad), ta in zip(reqs, arrivals):
+            dt = ta - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(srv.submit(pids[k], g, b, gradient=grad))
+
+    t0 = time.perf_counter()
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    for t in tickets:
+        srv.wait(t)
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    # the same requests, one at a time (max_in_flight = 1, same server path)
+    srv.close()
+    seq = q.QAOAServer(arena_bytes=160 << 30, num_streams=1, max_in_flight=1)
+    spids = {k: seq.add_problem(n, terms) for k, (n, terms) in probs.items()}
+    t1 = time.perf_counter()
+    for k, g, b, grad in reqs:
+        seq.wait(seq.submit(spids[k], g, b, gradient=grad))
+    t_seq = time.perf_counter() - t1
+    seq.close()
+    return {"metric": "served QAOA requests/s (60% objective / 40% gradient, n 16..30, p 1..20)",
+            "value": st["completed"] / wall, "unit": "requests/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "serve_mix", "requests": len(reqs), "rate_per_s": args.rate, "state": "complex64",
+                       "streams": 4, "max_in_flight": 16},
+            "p50_ms": 1e3 * st["p50_s"], "p99_ms": 1e3 * st["p99_s"], "mean_ms": 1e3 * st["mean_s"],
+            "peak_arena_GB": st["peak_bytes"] / 1e9, "sequential_requests_per_s": len(reqs) / t_seq}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", choices=sorted(CONFIGS), default="labs26")
+    ap.add_argument("--config", choices=sorted(CONFIGS) + ["batch", "serve"], default="labs26")
+    ap.add_argument("--sets-per-pass", type=int, default=0, help="batch: states advanced together (0 = autotune)")
+    ap.add_argument("--requests", type=int, default=120, help="serve: number of requests")
+    ap.add_argument("--rate", type=float, default=40.0, help="serve: Poisson arrival rate (requests/s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -105,6 +227,12 @@ def main(argv=None):
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration": {"bytes_read": nbytes, "bytes_written": nbytes, "dispatches": 3}}))
+        return 0
+
+    if args.config in ("batch", "serve") and args.gpus == 1:
+        import torch  # noqa: F401
+        res = bench_batch(args) if args.config == "batch" else bench_serve(args)
+        print(json.dumps(res), flush=True)
         return 0
 
     if args.gpus != 1:

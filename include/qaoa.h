@@ -208,6 +208,51 @@ int qaoa_grad(int n, int p, const double *gamma, const double *beta,
 int qaoa_grad_workspace_bytes(int n, int p, int state_dtype, int diag_dtype, size_t *bytes);
 
 /*
+ * Request loop (continuous batching) for an outer optimiser's objective and
+ * gradient queries (Section 2 / Fig. 1: the angles are tuned by repeated
+ * evaluations).  Cost vectors are precomputed once per problem and stay
+ * resident.  A scheduler thread admits queued requests in arrival order as soon
+ * as their device footprint (state, second state for gradients, workspace,
+ * output) fits the arena and an in-flight slot is free, runs them on a pool of
+ * streams so that independent requests overlap on the GPU, and retires them
+ * when their completion events fire, freeing memory for later admissions.
+ * Results do not depend on the mix: each request owns its buffers and every
+ * reduction has a fixed order.  The server allocates its arena (one device
+ * allocation), its streams and pinned result slots at creation only.
+ */
+typedef struct qaoa_server qaoa_server;
+
+typedef struct {
+    uint64_t submitted, completed, failed, queued, in_flight;
+    uint64_t arena_bytes, peak_bytes;  /* arena size, peak bytes in use */
+    double p50_s, p99_s, mean_s, max_s; /* latency submit -> result on the host */
+    double busy_s;                      /* first submit -> last completion */
+    double requests_per_s;              /* completed / busy_s */
+} qaoa_server_stats;
+
+/* arena_bytes >= 1 MiB of device memory for cost vectors and request buffers;
+ * 1 <= num_streams <= 64 (default priority); 1 <= max_in_flight <= 4096. */
+int qaoa_server_create(size_t arena_bytes, int num_streams, int max_in_flight, qaoa_server **out);
+/* Finishes queued and in-flight requests, then releases everything. */
+int qaoa_server_destroy(qaoa_server *s);
+/* Precompute a problem's cost vector into the arena (synchronous); terms as in
+ * qaoa_precompute_diag.  Returns its id in *problem_id. */
+int qaoa_server_add_problem(qaoa_server *s, int n, int64_t num_terms, const double *w,
+                            const int64_t *term_ptr, const int32_t *term_idx, int diag_dtype,
+                            int *problem_id);
+/* Queue one request: kind 0 = objective (result E, sum |psi|^2), kind 1 =
+ * gradient (result E, dE/dgamma[p], dE/dbeta[p]); 1 <= p <= 256; host angles are
+ * copied.  QAOA_ERR_NOMEM if the request could never fit the arena. */
+int qaoa_server_submit(qaoa_server *s, int problem_id, int kind, int state_dtype, int p,
+                       const double *gamma, const double *beta, int64_t *ticket);
+/* Block until the request finishes; copies its result (2 or 1 + 2p doubles)
+ * into out (out_len doubles) and its latency in seconds.  A ticket can be
+ * waited on once. */
+int qaoa_server_wait(qaoa_server *s, int64_t ticket, double *out, int out_len, double *latency_s);
+int qaoa_server_stats_get(qaoa_server *s, qaoa_server_stats *out);
+int qaoa_server_reset_stats(qaoa_server *s);
+
+/*
  * qaoa_plan_describe -- diagnostic: the HBM sweep plan used for n qubits.
  * kind 0: qaoa_evolve / qaoa_evolve_batch sweeps for state_dtype;
  * kind 1: the reverse sweeps of qaoa_grad for state_dtype;

@@ -22,7 +22,9 @@ QAOA_MAX_QUBITS = 34
 
 EXPORTS = ("qaoa_version", "qaoa_last_error", "qaoa_workspace_bytes", "qaoa_precompute_diag",
            "qaoa_evolve", "qaoa_expectation", "qaoa_grad", "qaoa_plan_describe", "qaoa_evolve_batch",
-           "qaoa_batch_workspace_bytes", "qaoa_grad_workspace_bytes")
+           "qaoa_batch_workspace_bytes", "qaoa_grad_workspace_bytes", "qaoa_server_create",
+           "qaoa_server_destroy", "qaoa_server_add_problem", "qaoa_server_submit", "qaoa_server_wait",
+           "qaoa_server_stats_get", "qaoa_server_reset_stats")
 
 _STATUS_NAMES = {0: "QAOA_OK", 1: "QAOA_ERR_INVALID", 2: "QAOA_ERR_RANGE", 3: "QAOA_ERR_NOMEM",
                  4: "QAOA_ERR_DEVICE", 5: "QAOA_ERR_UNSUPPORTED"}

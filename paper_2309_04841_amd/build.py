@@ -26,7 +26,7 @@ FLAGS = [
     "-Wl,-rpath,/opt/rocm/lib",
 ]
 
-SOURCES = [os.path.join(CSRC, "qaoa.hip")]
+SOURCES = [os.path.join(CSRC, "qaoa.hip"), os.path.join(CSRC, "server.hip")]
 
 
 def build(verbose: bool = False) -> str:

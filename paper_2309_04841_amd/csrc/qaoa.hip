@@ -440,9 +440,15 @@ double table_base(int diag_dtype, double diag_offset) {
 
 }  // namespace
 
+// Used by the request loop (server.hip) to report errors through qaoa_last_error().
+__attribute__((visibility("hidden"))) int qaoa_internal_set_error(int code, const char* msg) {
+  g_err = msg;
+  return code;
+}
+
 extern "C" {
 
-const char* qaoa_version(void) { return "0.1.0"; }
+const char* qaoa_version(void) { return "0.2.0"; }
 
 const char* qaoa_last_error(void) { return g_err.c_str(); }
 

@@ -265,3 +265,15 @@ def test_lds_swizzle_conflict_free(sdt, elem):
     assert used
     for tb, w in sorted(used):
         assert bank_conflict_degree(elem, tb, w) == 1, (tb, w)
+
+
+def test_server_validation():
+    h = ctypes.c_void_p()
+    lib = _lib.lib
+    lib.qaoa_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]
+    assert lib.qaoa_server_create(0, 1, 1, ctypes.byref(h)) == _lib.QAOA_ERR_INVALID
+    assert lib.qaoa_server_create(1 << 30, 0, 1, ctypes.byref(h)) == _lib.QAOA_ERR_INVALID
+    assert lib.qaoa_server_create(1 << 30, 1, 0, ctypes.byref(h)) == _lib.QAOA_ERR_INVALID
+    assert b"max_in_flight" in lib.qaoa_last_error()
+    lib.qaoa_server_destroy.argtypes = [ctypes.c_void_p]
+    assert lib.qaoa_server_destroy(None) == _lib.QAOA_ERR_INVALID
