@@ -260,9 +260,10 @@ int qaoa_server_reset_stats(qaoa_server *s);
  * Writes up to `cap` ints:
  *   [0] number of sweeps S, [1] register bits per thread EB, [2] 1 if the whole
  *   vector is one tile (all layers in one launch), then per sweep:
- *   tb, P, q0, w_store, nchunks, and nchunks triples (w, jlo, jhi).
- * Tile bits [0,P) are global bits [0,P); tile bits [P,tb) are global bits
- * [q0, q0+tb-P); a chunk butterflies tile bits [w+jlo, w+jhi).
+ *   tb, R, hA, qA, qB, act_lo, w_store, nchunks, and nchunks triples (w, jlo, jhi).
+ * Tile bits [0,R) are global bits [0,R); tile bits [R,R+hA) are global bits
+ * [qA,qA+hA); tile bits [R+hA,tb) are global bits [qB,qB+tb-R-hA); tile bits
+ * [act_lo,tb) are the sweep's qubits; a chunk butterflies tile bits [w+jlo, w+jhi).
  * Returns the number of ints needed (may exceed cap), or -QAOA_ERR_INVALID.
  */
 int qaoa_plan_describe(int kind, int n, int state_dtype, int elem_bytes, int *out, int cap);

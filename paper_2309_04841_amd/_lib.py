@@ -129,7 +129,7 @@ PLAN_EVOLVE, PLAN_ADJOINT, PLAN_TRANSFORM = 0, 1, 2
 
 
 def plan_describe(n: int, state_dtype: int = QAOA_C128, elem_bytes: int = 0, kind: int | None = None) -> dict:
-    """The sweep plan as a dict: {'eb', 'single', 'sweeps': [{'tb','P','q0','w_store','chunks'}]}.
+    """The sweep plan as a dict: {'eb', 'single', 'sweeps': [{'tb','R','hA','qA','qB','act_lo','w_store','chunks'}]}.
     kind: PLAN_EVOLVE (default), PLAN_ADJOINT, or PLAN_TRANSFORM (elem_bytes)."""
     if kind is None:
         kind = PLAN_TRANSFORM if state_dtype < 0 else PLAN_EVOLVE
@@ -143,11 +143,11 @@ def plan_describe(n: int, state_dtype: int = QAOA_C128, elem_bytes: int = 0, kin
     i = 3
     sweeps = []
     for _ in range(ns):
-        tb, P, q0, ws, nc = v[i:i + 5]
-        i += 5
+        tb, R, hA, qA, qB, act_lo, ws, nc = v[i:i + 8]
+        i += 8
         chunks = [tuple(v[i + 3 * c:i + 3 * c + 3]) for c in range(nc)]
         i += 3 * nc
-        sweeps.append(dict(tb=tb, P=P, q0=q0, w_store=ws, chunks=chunks))
+        sweeps.append(dict(tb=tb, R=R, hA=hA, qA=qA, qB=qB, act_lo=act_lo, w_store=ws, chunks=chunks))
     return dict(eb=eb, single=bool(single), sweeps=sweeps)
 
 

@@ -296,14 +296,13 @@ template <class S, class D, int EB>
 __device__ __forceinline__ void apply_phase(double (&vr)[1 << EB], double (&vi)[1 << EB], const SweepArgs& a,
                                             const LayerParams& lp, uint64_t base, uint32_t tid, int w, double2* tab) {
   constexpr int E = 1 << EB;
-  const int P = a.g.P, q0 = a.g.q0;
-  const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), P, q0);
+  const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g);
   if constexpr (D::kTable) {
     // raw stored values; the fallback recomputes c from them, so no address is
     // kept alive across the barrier
     int32_t raw[E];
 #pragma unroll
-    for (int k = 0; k < E; ++k) raw[k] = D::raw(a.diag, xb + tile_off((uint32_t)k << w, P, q0));
+    for (int k = 0; k < E; ++k) raw[k] = D::raw(a.diag, xb + tile_off((uint32_t)k << w, a.g));
     int ok = 1;
     if constexpr (!D::kAlwaysInTable) {
 #pragma unroll
@@ -340,7 +339,7 @@ __device__ __forceinline__ void apply_phase(double (&vr)[1 << EB], double (&vi)[
   } else {
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-      const double c = D::get(a.diag, xb + tile_off((uint32_t)k << w, P, q0)) + a.diag_offset;
+      const double c = D::get(a.diag, xb + tile_off((uint32_t)k << w, a.g)) + a.diag_offset;
       const double2 f = phase_direct(lp.g, c);
       cmul_inplace(vr[k], vi[k], f.x, f.y);
     }
@@ -376,10 +375,10 @@ template <class D, int EB>
 __device__ __forceinline__ void expv_partials(const double (&vr)[1 << EB], const double (&vi)[1 << EB],
                                               const SweepArgs& a, uint64_t base, uint32_t tid, int w,
                                               double& e_part, double& n_part) {
-  const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g.P, a.g.q0);
+  const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g);
 #pragma unroll
   for (int k = 0; k < (1 << EB); ++k) {
-    const double c = D::get(a.diag, xb + tile_off((uint32_t)k << w, a.g.P, a.g.q0)) + a.diag_offset;
+    const double c = D::get(a.diag, xb + tile_off((uint32_t)k << w, a.g)) + a.diag_offset;
     const double pr = vr[k] * vr[k] + vi[k] * vi[k];
     e_part += pr * c;
     n_part += pr;
@@ -398,8 +397,7 @@ __global__ void __launch_bounds__(512, S::kMinWavesPerSimd) qaoa_sweep_kernel(co
   typename S::L* lds = reinterpret_cast<typename S::L*>(smem_raw);
   double2* tab = reinterpret_cast<double2*>(smem_raw + (1u << a.g.tb) * S::kBytes);
   const uint32_t tid = threadIdx.x;
-  const int P = a.g.P, q0 = a.g.q0;
-  const uint64_t base = block_base(blockIdx.x, a.g.tb, P, q0);
+  const uint64_t base = block_base(blockIdx.x, a.g);
   const uint32_t set = blockIdx.y;
   void* psi = reinterpret_cast<char*>(a.psi) + (uint64_t)set * a.set_stride_bytes;
   const LayerParams lp = layer_params(a, set, 0);
@@ -411,17 +409,17 @@ __global__ void __launch_bounds__(512, S::kMinWavesPerSimd) qaoa_sweep_kernel(co
   // mapping, and the tile returns to that mapping for the reduction
   typename D::RawT cv[EXPV ? E : 1];
   {
-    const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), P, q0);
+    const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g);
     if constexpr (INIT) {
 #pragma unroll
       for (int k = 0; k < E; ++k) { vr[k] = a.amp0; vi[k] = 0.0; }
     } else {
 #pragma unroll
-      for (int k = 0; k < E; ++k) S::load(psi, xb + tile_off((uint32_t)k << w, P, q0), vr[k], vi[k]);
+      for (int k = 0; k < E; ++k) S::load(psi, xb + tile_off((uint32_t)k << w, a.g), vr[k], vi[k]);
     }
     if constexpr (EXPV) {
 #pragma unroll
-      for (int k = 0; k < E; ++k) cv[k] = D::load_raw(a.diag, xb + tile_off((uint32_t)k << w, P, q0));
+      for (int k = 0; k < E; ++k) cv[k] = D::load_raw(a.diag, xb + tile_off((uint32_t)k << w, a.g));
     }
   }
   if constexpr (PHASE) apply_phase<S, D, EB>(vr, vi, a, lp, base, tid, w, tab);
@@ -442,9 +440,9 @@ __global__ void __launch_bounds__(512, S::kMinWavesPerSimd) qaoa_sweep_kernel(co
     }
   }
   {
-    const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), P, q0);
+    const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g);
 #pragma unroll
-    for (int k = 0; k < E; ++k) S::store(psi, xb + tile_off((uint32_t)k << w, P, q0), vr[k], vi[k]);
+    for (int k = 0; k < E; ++k) S::store(psi, xb + tile_off((uint32_t)k << w, a.g), vr[k], vi[k]);
   }
   if constexpr (EXPV) {
     block_sum2(e_part, n_part, reinterpret_cast<double*>(smem_raw));
@@ -608,8 +606,7 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_kernel(const AdjArgs a) {
   typename S::L* lds = reinterpret_cast<typename S::L*>(smem_raw);
   double2* tab = reinterpret_cast<double2*>(smem_raw + (1u << a.g.tb) * S::kBytes);
   const uint32_t tid = threadIdx.x;
-  const int P = a.g.P, q0 = a.g.q0;
-  const uint64_t base = block_base(blockIdx.x, a.g.tb, P, q0);
+  const uint64_t base = block_base(blockIdx.x, a.g);
   const size_t r = (size_t)a.layer;
   const LayerParams lp{a.pset[3 * r], a.pset[3 * r + 1], a.pset[3 * r + 2], a.ptab + r * kTabEntries};
   const int w_load = a.g.tb - EB;
@@ -617,12 +614,12 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_kernel(const AdjArgs a) {
   double vr[E], vi[E], lr[E], li[E];
   typename D::RawT cv[(FIRST || PHASE) ? E : 1];
   {
-    const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), P, q0);
+    const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g);
 #pragma unroll
-    for (int k = 0; k < E; ++k) S::load(a.psi, xb + tile_off((uint32_t)k << w, P, q0), vr[k], vi[k]);
+    for (int k = 0; k < E; ++k) S::load(a.psi, xb + tile_off((uint32_t)k << w, a.g), vr[k], vi[k]);
     if constexpr (FIRST || PHASE) {
 #pragma unroll
-      for (int k = 0; k < E; ++k) cv[k] = D::load_raw(a.diag, xb + tile_off((uint32_t)k << w, P, q0));
+      for (int k = 0; k < E; ++k) cv[k] = D::load_raw(a.diag, xb + tile_off((uint32_t)k << w, a.g));
     }
     if constexpr (FIRST) {
 #pragma unroll
@@ -633,7 +630,7 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_kernel(const AdjArgs a) {
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < E; ++k) S::load(a.lam, xb + tile_off((uint32_t)k << w, P, q0), lr[k], li[k]);
+      for (int k = 0; k < E; ++k) S::load(a.lam, xb + tile_off((uint32_t)k << w, a.g), lr[k], li[k]);
     }
   }
   double xacc = 0.0, gacc = 0.0;
@@ -646,10 +643,10 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_kernel(const AdjArgs a) {
   }
   if constexpr (PHASE) undo_phase<D, EB>(vr, vi, lr, li, cv, a, lp, tab, tid, gacc);
   {
-    const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), P, q0);
+    const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g);
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-      const uint64_t x = xb + tile_off((uint32_t)k << w, P, q0);
+      const uint64_t x = xb + tile_off((uint32_t)k << w, a.g);
       S::store(a.psi, x, vr[k], vi[k]);
       S::store(a.lam, x, lr[k], li[k]);
     }
@@ -784,12 +781,11 @@ __global__ void __launch_bounds__(512) fwht_sweep_kernel(const FwhtArgs a) {
   T* lds = reinterpret_cast<T*>(smem_raw);
   T* data = reinterpret_cast<T*>(a.data);
   const uint32_t tid = threadIdx.x;
-  const int P = a.g.P, q0 = a.g.q0;
-  const uint64_t base = block_base(blockIdx.x, a.g.tb, P, q0);
+  const uint64_t base = block_base(blockIdx.x, a.g);
   R v[E];
   int w = a.g.tb - EB;
 #pragma unroll
-  for (int k = 0; k < E; ++k) v[k] = (R)data[base + tile_off(tmap<EB>(tid, k, w), P, q0)];
+  for (int k = 0; k < E; ++k) v[k] = (R)data[base + tile_off(tmap<EB>(tid, k, w), a.g)];
   for (int ci = 0; ci < a.g.nchunks; ++ci) {
     const Chunk ch = a.g.chunk[ci];
     if (ch.w != w) {
@@ -824,7 +820,7 @@ __global__ void __launch_bounds__(512) fwht_sweep_kernel(const FwhtArgs a) {
     w = a.g.w_store;
   }
 #pragma unroll
-  for (int k = 0; k < E; ++k) data[base + tile_off(tmap<EB>(tid, k, w), P, q0)] = (T)v[k];
+  for (int k = 0; k < E; ++k) data[base + tile_off(tmap<EB>(tid, k, w), a.g)] = (T)v[k];
 }
 
 // ----------------------------------------------------------------------------

@@ -68,13 +68,13 @@ int min_passenger_bits(size_t elem_bytes) {
 // then the remaining active bits bottom-up; the tile is stored from the last
 // window if that window keeps >= 2^store_min_bits contiguous elements per run,
 // else it is exchanged back to the load window first.
-qk::TileGeom make_geom(int tb, int P, int q0, int eb, bool low, int store_min_bits) {
+qk::TileGeom make_geom(int tb, int R, int hA, int qA, int qB, int act_lo, int eb, int store_min_bits) {
   qk::TileGeom g{};
-  g.tb = tb; g.P = P; g.q0 = q0; g.nchunks = 0;
+  g.tb = tb; g.R = R; g.hA = hA; g.qA = qA; g.qB = qB; g.act_lo = act_lo; g.nchunks = 0;
   const int top_w = tb - eb;
-  const int lo0 = std::max(P, top_w);
+  const int lo0 = std::max(act_lo, top_w);
   g.chunk[g.nchunks++] = qk::Chunk{(int8_t)top_w, (int8_t)(lo0 - top_w), (int8_t)eb, 0};
-  int rlo = P;
+  int rlo = act_lo;
   const int rhi = lo0;
   while (rlo < rhi) {
     const int chi = std::min(rlo + eb, rhi);
@@ -83,8 +83,7 @@ qk::TileGeom make_geom(int tb, int P, int q0, int eb, bool low, int store_min_bi
     rlo = chi;
   }
   const int last_w = g.chunk[g.nchunks - 1].w;
-  const int contig = low ? tb : P;
-  g.w_store = (std::min(last_w, contig) >= store_min_bits || last_w == top_w) ? last_w : top_w;
+  g.w_store = (std::min(last_w, R) >= store_min_bits || last_w == top_w) ? last_w : top_w;
   return g;
 }
 
@@ -95,6 +94,19 @@ struct Plan {
   std::vector<qk::TileGeom> sweeps;
 };
 
+// Qubits at or above this bit select the 2 MiB page of an element.
+int page_bit(size_t elem_bytes) {
+  int b = 0;
+  while (((size_t)1 << (b + 1)) * elem_bytes <= ((size_t)2 << 20)) ++b;
+  return b;
+}
+
+// The first sweep of a layer takes the contiguous low qubits [0, R0) plus m0
+// qubits at the top; the other sweeps take P passengers [0, P) plus a segment
+// of the remaining low qubits and a segment of the remaining page-selecting
+// qubits.  m0 and the split are chosen to minimise the largest number of
+// page-selecting qubits in any sweep (2^that = pages a workgroup touches),
+// keeping the sweep count of the plain split.
 Plan make_plan(int n, size_t elem_bytes, int eb = kEB) {
   Plan pl;
   const int tbmax = tile_bits_for_bytes(elem_bytes, 9 + eb);
@@ -103,20 +115,48 @@ Plan make_plan(int n, size_t elem_bytes, int eb = kEB) {
   if (n <= tbmax) {
     pl.single = true;
     pl.eb = std::min(eb, n);
-    pl.sweeps.push_back(make_geom(n, 0, 0, pl.eb, true, 0));
+    pl.sweeps.push_back(make_geom(n, n, 0, n, n, 0, pl.eb, 0));
     return pl;
   }
   pl.single = false;
   pl.eb = eb;
-  pl.sweeps.push_back(make_geom(tbmax, 0, 0, eb, true, smin));
-  const int r = n - tbmax;
   const int hmax = tbmax - pmin;
-  const int ns = (r + hmax - 1) / hmax;
-  int q = tbmax;
-  for (int i = 0; i < ns; ++i) {
-    const int h = r / ns + (i < r % ns ? 1 : 0);
-    pl.sweeps.push_back(make_geom(tbmax, tbmax - h, q, eb, false, smin));
-    q += h;
+  const int k = 1 + (n - tbmax + hmax - 1) / hmax;  // sweeps per layer
+  const int pb = std::max(page_bit(elem_bytes), tbmax);
+  const int npage = std::max(0, n - pb);
+  const int r0_min = std::max(pmin + 4, tbmax - 6);
+  int best_m0 = 0, best_cost = 1 << 30;
+  std::vector<int> best_h, best_b;
+  for (int m0 = 0; tbmax - m0 >= r0_min && m0 <= npage; ++m0) {
+    const int R0 = tbmax - m0;
+    const int T = n - m0 - R0;  // qubits left for the other sweeps
+    if (T > (k - 1) * hmax) continue;
+    std::vector<int> h(k - 1), b(k - 1);
+    for (int i = 0; i < k - 1; ++i) h[i] = T / (k - 1) + (i < T % (k - 1) ? 1 : 0);
+    int rem = npage - m0;
+    bool ok = true;
+    for (int i = 0; i < k - 1; ++i) {
+      const int share = rem / (k - 1 - i) + (rem % (k - 1 - i) ? 1 : 0);
+      b[i] = std::min(share, h[i]);
+      rem -= b[i];
+      if (h[i] < m0 && m0 > 0) ok = false;  // passengers [0, tbmax - h) must stay inside [0, R0)
+    }
+    if (rem != 0 || !ok) continue;
+    int cost = m0;
+    for (int i = 0; i < k - 1; ++i) cost = std::max(cost, b[i]);
+    if (cost < best_cost) { best_cost = cost; best_m0 = m0; best_h = h; best_b = b; }
+  }
+  const int m0 = best_m0, R0 = tbmax - m0;
+  // first sweep: run [0, R0) + segment [n - m0, n), all active
+  pl.sweeps.push_back(make_geom(tbmax, R0, m0, n - m0, n, 0, eb, smin));
+  int xa = R0, xb = std::max(pb, R0);
+  for (int i = 0; i < k - 1; ++i) {
+    const int h = best_h[i], bpage = best_b[i], a = h - bpage, P = tbmax - h;
+    const int qA = a ? xa : xb;         // an empty segment A sits where B starts
+    const int qB = bpage ? xb : qA + a;  // an empty segment B sits where A ends
+    pl.sweeps.push_back(make_geom(tbmax, P, a, qA, qB, P, eb, smin));
+    xa += a;
+    xb += bpage;
   }
   return pl;
 }
@@ -867,7 +907,8 @@ int qaoa_plan_describe(int kind, int n, int state_dtype, int elem_bytes, int* ou
   v.push_back(pl.eb);
   v.push_back(pl.single ? 1 : 0);
   for (const auto& g : pl.sweeps) {
-    v.push_back(g.tb); v.push_back(g.P); v.push_back(g.q0); v.push_back(g.w_store); v.push_back(g.nchunks);
+    v.push_back(g.tb); v.push_back(g.R); v.push_back(g.hA); v.push_back(g.qA); v.push_back(g.qB);
+    v.push_back(g.act_lo); v.push_back(g.w_store); v.push_back(g.nchunks);
     for (int c = 0; c < g.nchunks; ++c) { v.push_back(g.chunk[c].w); v.push_back(g.chunk[c].jlo); v.push_back(g.chunk[c].jhi); }
   }
   if (out) for (int i = 0; i < (int)v.size() && i < cap; ++i) out[i] = v[i];

@@ -1,14 +1,17 @@
 // tile.hpp -- tiled in-place butterfly sweeps over a 2^n vector (gfx950).
 //
 // A "sweep" is one read + one write of the whole vector.  Each workgroup owns
-// one tile of 2^tb elements.  The tile's index bits map to global index bits as
-//   tile bits [0, P)   -> global bits [0, P)          (passengers: contiguous,
-//                                                      never butterflied in a
-//                                                      high sweep)
-//   tile bits [P, tb)  -> global bits [q0, q0+tb-P)   (active qubits)
-// and the workgroup index fills the remaining global bits (first [P, q0), then
-// [q0+tb-P, n)).  A "low" sweep has P = 0, q0 = 0: a contiguous tile whose bits
-// are all active.
+// one tile of 2^tb elements.  Tile bits map to global index bits as
+//   tile bits [0, R)              -> global bits [0, R)       (the contiguous run)
+//   tile bits [R, R + hA)         -> global bits [qA, qA + hA)  (segment A)
+//   tile bits [R + hA, tb)        -> global bits [qB, qB + hB)  (segment B)
+// with R <= qA, qA + hA <= qB, qB + hB <= n, and the workgroup index fills the
+// remaining global bits in increasing order.  Tile bits [act_lo, tb) are the
+// active qubits of the sweep: act_lo = 0 in the first sweep of a layer (the
+// run is active too), act_lo = R in the others (the run's qubits are only
+// passengers that make each row a contiguous burst).  Two segments let the
+// planner spread the qubits above the 2 MiB page boundary over all sweeps, so
+// no sweep touches hundreds of pages per workgroup.
 //
 // Every thread holds 2^EB elements in registers.  For a register "window" w the
 // thread's k-th element is tile element
@@ -39,8 +42,10 @@ struct Chunk {
 
 struct TileGeom {
   int tb;       // tile bits
-  int P;        // passenger bits
-  int q0;       // global bit of tile bit P
+  int R;        // contiguous run: tile bits [0, R) = global bits [0, R)
+  int hA, qA;   // segment A: tile bits [R, R + hA) = global bits [qA, qA + hA)
+  int qB;       // segment B: tile bits [R + hA, tb) = global bits [qB, qB + tb - R - hA)
+  int act_lo;   // active tile bits [act_lo, tb)
   int nchunks;  // chunks per layer
   int w_store;  // window the tile is stored from
   Chunk chunk[kMaxChunks];
@@ -62,17 +67,22 @@ __device__ __forceinline__ uint32_t thr_part(uint32_t tid, int w) {
 // tile bits to disjoint global bits, so tile_off(a | b) = tile_off(a) +
 // tile_off(b) for disjoint a, b: addresses split into a per-thread part and a
 // per-register part that is uniform across the workgroup.
-__device__ __forceinline__ uint64_t tile_off(uint32_t t, int P, int q0) {
-  const uint32_t pm = (1u << P) - 1u;
-  return (uint64_t)(t & pm) | ((uint64_t)(t >> P) << q0);
+__device__ __forceinline__ uint64_t tile_off(uint32_t t, const TileGeom& g) {
+  const uint32_t rm = (1u << g.R) - 1u, am = (1u << g.hA) - 1u;
+  return (uint64_t)(t & rm) | ((uint64_t)((t >> g.R) & am) << g.qA) | ((uint64_t)(t >> (g.R + g.hA)) << g.qB);
 }
 
-// Global index of element 0 of block b.
-__device__ __forceinline__ uint64_t block_base(uint64_t b, int tb, int P, int q0) {
-  const int nlow = q0 - P;
-  const uint64_t blo = b & ((1ull << nlow) - 1ull);
-  const uint64_t bhi = b >> nlow;
-  return (blo << P) | (bhi << (q0 + tb - P));
+// Global index of element 0 of block b: b's bits fill the gaps [R, qA),
+// [qA + hA, qB) and [qB + hB, n) in that order.
+__device__ __forceinline__ uint64_t block_base(uint64_t b, const TileGeom& g) {
+  const int g1 = g.qA - g.R;
+  const int g2 = g.qB - (g.qA + g.hA);
+  const int topB = g.qB + (g.tb - g.R - g.hA);
+  const uint64_t lo = b & ((1ull << g1) - 1ull);
+  b >>= g1;
+  const uint64_t mid = b & ((1ull << g2) - 1ull);
+  b >>= g2;
+  return (lo << g.R) | (mid << (g.qA + g.hA)) | (b << topB);
 }
 
 // LDS position of tile element t: pos = t ^ L(t >> S), L linear over GF(2)

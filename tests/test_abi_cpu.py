@@ -145,13 +145,31 @@ def tmap(tid, k, w, eb):
     return (tid & ((1 << w) - 1)) | (k << w) | ((tid >> w) << (w + eb))
 
 
-def tile_off(t, P, q0):
-    return (t & ((1 << P) - 1)) | ((t >> P) << q0)
+def tile_off(t, s):
+    t = np.asarray(t)
+    R, hA, qA, qB = s["R"], s["hA"], s["qA"], s["qB"]
+    return (t & ((1 << R) - 1)) | (((t >> R) & ((1 << hA) - 1)) << qA) | ((t >> (R + hA)) << qB)
 
 
-def block_base(b, tb, P, q0):
-    nlow = q0 - P
-    return ((b & ((1 << nlow) - 1)) << P) | ((b >> nlow) << (q0 + tb - P))
+def block_base(b, s):
+    R, hA, qA, qB, tb = s["R"], s["hA"], s["qA"], s["qB"], s["tb"]
+    g1, g2 = qA - R, qB - (qA + hA)
+    top = qB + (tb - R - hA)
+    b = np.asarray(b)
+    lo = b & ((1 << g1) - 1)
+    b = b >> g1
+    mid = b & ((1 << g2) - 1)
+    b = b >> g2
+    return (lo << R) | (mid << (qA + hA)) | (b << top)
+
+
+def global_bit(s, t):
+    R, hA, qA, qB = s["R"], s["hA"], s["qA"], s["qB"]
+    if t < R:
+        return t
+    if t < R + hA:
+        return qA + (t - R)
+    return qB + (t - R - hA)
 
 
 # LDS swizzle pos = t ^ L(t >> S), L given by its columns (GF(2)-linear)
@@ -188,21 +206,26 @@ def _check_plan(n, plan, elem_bytes, emulate):
     eb = plan["eb"]
     seen = []
     for si, s in enumerate(plan["sweeps"]):
-        tb, P, q0 = s["tb"], s["P"], s["q0"]
-        assert 1 <= tb <= n and 0 <= P <= tb
+        tb, R, hA, qA, qB, act_lo = s["tb"], s["R"], s["hA"], s["qA"], s["qB"], s["act_lo"]
+        hB = tb - R - hA
+        assert 1 <= tb <= n and 0 <= R <= tb and 0 <= hA and hB >= 0
         assert tb - eb <= 9, "more than 512 threads"
         assert (1 << tb) * elem_bytes <= 65536, "tile exceeds 64 KiB of LDS"
+        assert R <= qA and qA + hA <= qB and qB + hB <= n, "segments must be ordered and inside n"
         if si == 0:
-            assert P == 0 and q0 == 0
-        assert q0 >= P and q0 + (tb - P) <= n
+            assert act_lo == 0
+        else:
+            assert act_lo == R and (1 << R) * elem_bytes >= 128, "high sweeps move >= 128 contiguous bytes"
+        gbits = [global_bit(s, t) for t in range(tb)]
+        assert len(set(gbits)) == tb and max(gbits) < n
         assert 0 <= s["w_store"] <= tb - eb
         assert s["chunks"][0][0] == tb - eb, "first window must be the load mapping"
         for (w, jlo, jhi) in s["chunks"]:
             assert 0 <= w <= tb - eb and 0 <= jlo < jhi <= eb
             for j in range(jlo, jhi):
                 t = w + j
-                assert t >= P, "butterfly on a passenger bit"
-                seen.append(q0 + (t - P))
+                assert t >= act_lo, "butterfly on a passenger bit"
+                seen.append(gbits[t])
         if emulate:
             nthreads = 1 << (tb - eb)
             tid = np.arange(nthreads)[:, None]
@@ -213,12 +236,31 @@ def _check_plan(n, plan, elem_bytes, emulate):
                 assert np.array_equal(np.sort(t), np.arange(1 << tb))
                 pos = swz(t, elem_bytes)
                 assert np.array_equal(np.sort(pos), np.arange(1 << tb))
-                off = tile_off(t, P, q0)
+                off = tile_off(t, s)
                 blocks = np.arange(1 << (n - tb))[:, None]
-                g = (block_base(blocks, tb, P, q0) | off[None, :]).ravel()
+                g = (block_base(blocks, s) | off[None, :]).ravel()
                 assert g.min() >= 0 and g.max() < (1 << n)
                 assert np.array_equal(np.sort(g), np.arange(1 << n)), "sweep does not cover every element once"
+                # the split into per-thread and per-register parts used by the kernels
+                thr = (tid & ((1 << w) - 1)) | ((tid >> w) << (w + eb))
+                assert np.array_equal(tile_off(thr | (k << w), s), tile_off(thr, s) + tile_off(k << w, s))
     assert sorted(seen) == list(range(n)), "every qubit must be butterflied exactly once per layer"
+
+
+def _page_bits_per_sweep(plan, elem_bytes):
+    pb = 0
+    while (1 << (pb + 1)) * elem_bytes <= (2 << 20):
+        pb += 1
+    return [sum(1 for t in range(s["tb"]) if global_bit(s, t) >= pb) for s in plan["sweeps"]]
+
+
+def test_page_bits_are_spread():
+    # LABS n=26 complex128 and n=31 complex64: no sweep's tile spans more than
+    # 2^5 pages of 2 MiB (the plain split had 2^7 and 2^9)
+    p26 = _lib.plan_describe(26, _lib.QAOA_C128)
+    p31 = _lib.plan_describe(31, _lib.QAOA_C64)
+    assert max(_page_bits_per_sweep(p26, 16)) <= 4
+    assert max(_page_bits_per_sweep(p31, 8)) <= 5
 
 
 @pytest.mark.parametrize("sdt,eb", [(_lib.QAOA_C128, 16), (_lib.QAOA_C64, 8)])
