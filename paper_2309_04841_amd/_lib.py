@@ -24,7 +24,7 @@ EXPORTS = ("qaoa_version", "qaoa_last_error", "qaoa_workspace_bytes", "qaoa_prec
            "qaoa_evolve", "qaoa_expectation", "qaoa_grad", "qaoa_plan_describe", "qaoa_evolve_batch",
            "qaoa_batch_workspace_bytes", "qaoa_grad_workspace_bytes", "qaoa_server_create",
            "qaoa_server_destroy", "qaoa_server_add_problem", "qaoa_server_submit", "qaoa_server_wait",
-           "qaoa_server_stats_get", "qaoa_server_reset_stats")
+           "qaoa_server_stats_get", "qaoa_server_reset_stats", "qaoa_schedule_describe")
 
 _STATUS_NAMES = {0: "QAOA_OK", 1: "QAOA_ERR_INVALID", 2: "QAOA_ERR_RANGE", 3: "QAOA_ERR_NOMEM",
                  4: "QAOA_ERR_DEVICE", 5: "QAOA_ERR_UNSUPPORTED"}
@@ -58,6 +58,8 @@ def _load() -> ctypes.CDLL:
     lib.qaoa_grad.argtypes = [I, I, P, P, P, I, D, SZ, P, P, I, SZ, P, P, SZ, P]
     lib.qaoa_plan_describe.restype = I
     lib.qaoa_plan_describe.argtypes = [I, I, I, I, P, I]
+    lib.qaoa_schedule_describe.restype = I
+    lib.qaoa_schedule_describe.argtypes = [I, I, I, I, I, P, I]
     lib.qaoa_grad_workspace_bytes.restype = I
     lib.qaoa_grad_workspace_bytes.argtypes = [I, I, I, I, ctypes.POINTER(SZ)]
     lib.qaoa_evolve_batch.restype = I
@@ -149,6 +151,20 @@ def plan_describe(n: int, state_dtype: int = QAOA_C128, elem_bytes: int = 0, kin
         i += 3 * nc
         sweeps.append(dict(tb=tb, R=R, hA=hA, qA=qA, qB=qB, act_lo=act_lo, w_store=ws, chunks=chunks))
     return dict(eb=eb, single=bool(single), sweeps=sweeps)
+
+
+F_INIT, F_PHASE, F_EXPV, F_FUSE = 1, 2, 4, 8
+
+
+def schedule_describe(n: int, p: int, state_dtype: int = QAOA_C128, init: bool = True, reduce: bool = True) -> list:
+    """Launch order of one evaluation: [(sweep, layer, flags)], empty for one-tile states."""
+    need = lib.qaoa_schedule_describe(n, p, state_dtype, int(init), int(reduce), None, 0)
+    if need < 0:
+        check(-need)
+    buf = (ctypes.c_int * max(need, 1))()
+    lib.qaoa_schedule_describe(n, p, state_dtype, int(init), int(reduce), buf, need)
+    v = list(buf)[:need]
+    return [tuple(v[i:i + 3]) for i in range(0, need, 3)]
 
 
 def workspace_bytes(op: int, n: int, state_dtype: int = QAOA_C128, diag_dtype: int = QAOA_DIAG_I32) -> int:

@@ -22,9 +22,12 @@
 namespace qk {
 
 constexpr int kMaxLayersPerLaunch = 32;
+// rows prepared per chunk of host angles: the chunk's layers and the next one
+// (a fused sweep at the end of a chunk reads the following layer's row)
+constexpr int kPrepRows = kMaxLayersPerLaunch + 1;
 constexpr int kScatterChunk = 240;
 
-enum : int { F_INIT = 1, F_PHASE = 2, F_EXPV = 4 };
+enum : int { F_INIT = 1, F_PHASE = 2, F_EXPV = 4, F_FUSE = 8 };
 
 // ----------------------------------------------------------------------------
 // element policies
@@ -140,7 +143,7 @@ constexpr int kTabEntries = 512;  // HI (256) then LO (256), double2 (cos, -sin)
 // and single evaluations use bit-identical values: row r gets
 // pset[3r..3r+2] = (gamma, cos beta, sin beta) and, when tab != nullptr, the
 // phase tables tab[512 r ..].  Angles come from device arrays (gamma_d, beta_d)
-// or, when those are null, from the kernel arguments (at most 32 rows).
+// or, when those are null, from the kernel arguments (at most kPrepRows rows).
 struct PrepArgs {
   const double* gamma_d;
   const double* beta_d;
@@ -148,8 +151,8 @@ struct PrepArgs {
   double2* tab;
   double base;   // table base + cost offset
   int rows;
-  double gamma[32];
-  double beta[32];
+  double gamma[kPrepRows];
+  double beta[kPrepRows];
 };
 
 __global__ void __launch_bounds__(256) layer_prep_kernel(const PrepArgs a) {
@@ -288,25 +291,20 @@ __device__ __forceinline__ void cmul_inplace(double& r, double& i, double fr, do
   r = nr; i = ni;
 }
 
-// Phase operator of layer l on the thread's register elements (window w).
-// Integer cost vectors use the LDS-staged tables; if any element of the
-// workgroup falls outside the table range the whole workgroup takes the
-// direct path (a workgroup-uniform branch).
+// Phase operator of one layer on the thread's register elements, from the
+// stored cost values `cv` of those elements.  Integer cost vectors use the
+// LDS-staged tables; if any element of the workgroup falls outside the table
+// range the whole workgroup takes the direct path (a workgroup-uniform branch).
 template <class S, class D, int EB>
-__device__ __forceinline__ void apply_phase(double (&vr)[1 << EB], double (&vi)[1 << EB], const SweepArgs& a,
-                                            const LayerParams& lp, uint64_t base, uint32_t tid, int w, double2* tab) {
+__device__ __forceinline__ void phase_from_raw(double (&vr)[1 << EB], double (&vi)[1 << EB],
+                                               const typename D::RawT (&cv)[1 << EB], const SweepArgs& a,
+                                               const LayerParams& lp, uint32_t tid, double2* tab) {
   constexpr int E = 1 << EB;
-  const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g);
   if constexpr (D::kTable) {
-    // raw stored values; the fallback recomputes c from them, so no address is
-    // kept alive across the barrier
-    int32_t raw[E];
-#pragma unroll
-    for (int k = 0; k < E; ++k) raw[k] = D::raw(a.diag, xb + tile_off((uint32_t)k << w, a.g));
     int ok = 1;
     if constexpr (!D::kAlwaysInTable) {
 #pragma unroll
-      for (int k = 0; k < E; ++k) ok &= (D::tab_index(raw[k]) >= 0);
+      for (int k = 0; k < E; ++k) ok &= (D::tab_index(cv[k]) >= 0);
     }
     for (uint32_t e = tid; e < (uint32_t)kTabEntries; e += blockDim.x) tab[e] = lp.tab[e];
     bool fast;
@@ -323,7 +321,7 @@ __device__ __forceinline__ void apply_phase(double (&vr)[1 << EB], double (&vi)[
       for (int k0 = 0; k0 < E; k0 += 4) {
 #pragma unroll
         for (int k = k0; k < k0 + 4 && k < E; ++k) {
-          const int32_t u = D::tab_index(raw[k]);
+          const int32_t u = D::tab_index(cv[k]);
           const double2 h = tab[u >> 8], lo = tab[256 + (u & 255)];
           cmul_inplace(vr[k], vi[k], fma(h.x, lo.x, -h.y * lo.y), fma(h.x, lo.y, h.y * lo.x));
         }
@@ -332,27 +330,37 @@ __device__ __forceinline__ void apply_phase(double (&vr)[1 << EB], double (&vi)[
     } else {
 #pragma unroll
       for (int k = 0; k < E; ++k) {
-        const double2 f = phase_direct(lp.g, (double)raw[k] + a.diag_offset);
+        const double2 f = phase_direct(lp.g, D::value(cv[k]) + a.diag_offset);
         cmul_inplace(vr[k], vi[k], f.x, f.y);
       }
     }
   } else {
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-      const double c = D::get(a.diag, xb + tile_off((uint32_t)k << w, a.g)) + a.diag_offset;
-      const double2 f = phase_direct(lp.g, c);
+      const double2 f = phase_direct(lp.g, D::value(cv[k]) + a.diag_offset);
       cmul_inplace(vr[k], vi[k], f.x, f.y);
     }
   }
 }
 
-// Mixer gates of one layer on the tile's active qubits, window by window.
-template <class S, int EB>
+// Stored cost values of the thread's register elements in window w.
+template <class D, int EB>
+__device__ __forceinline__ void load_cost(typename D::RawT (&cv)[1 << EB], const SweepArgs& a, uint64_t base,
+                                          uint32_t tid, int w) {
+  const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g);
+#pragma unroll
+  for (int k = 0; k < (1 << EB); ++k) cv[k] = D::load_raw(a.diag, xb + tile_off((uint32_t)k << w, a.g));
+}
+
+// Mixer gates of one layer on the tile's active qubits, window by window, in
+// chunk order or (REV) in reverse chunk order; the gates commute, so both
+// orders give the same layer.  Returns the final window.
+template <class S, int EB, bool REV = false>
 __device__ __forceinline__ int apply_mixer(double (&vr)[1 << EB], double (&vi)[1 << EB], typename S::L* lds,
                                            const TileGeom& g, uint32_t tid, int w, double ca, double sb) {
   constexpr int E = 1 << EB;
-  for (int ci = 0; ci < g.nchunks; ++ci) {
-    const Chunk ch = g.chunk[ci];
+  for (int i = 0; i < g.nchunks; ++i) {
+    const Chunk ch = g.chunk[REV ? g.nchunks - 1 - i : i];
     if (ch.w != w) {
       exchange_c<S, EB>(vr, vi, lds, tid, w, ch.w);
       w = ch.w;
@@ -385,19 +393,30 @@ __device__ __forceinline__ void expv_partials(const double (&vr)[1 << EB], const
   }
 }
 
-// One HBM sweep of one layer (multi-tile states).  The flags are compile-time
-// so each launch carries only the code it runs:
+// Workgroups are handed to the eight XCDs round robin.  Renumbered this way,
+// each XCD walks one contiguous range of tiles, so tiles that share cache
+// lines or pages run on the same XCD (and its L2) at about the same time.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+  if (nb & 7u) return b;
+  return (b & 7u) * (nb >> 3) + (b >> 3);
+}
+
+// One HBM sweep (multi-tile states).  The flags are compile-time so each
+// launch carries only the code it runs:
 //   INIT   generate |+> in registers instead of loading the state
 //   PHASE  apply the layer's phase before the mixer gates
 //   EXPV   emit per-workgroup (E, norm) partials of the result
-template <class S, class D, int EB, bool INIT, bool PHASE, bool EXPV>
+//   FUSE   the tile's mixer gates of layer l, the phase of layer l+1, then the
+//          tile's mixer gates of layer l+1 (valid when this sweep is the last
+//          of layer l: every other gate of layer l is already applied)
+template <class S, class D, int EB, bool INIT, bool PHASE, bool EXPV, bool FUSE>
 __global__ void __launch_bounds__(512, S::kMinWavesPerSimd) qaoa_sweep_kernel(const SweepArgs a) {
   constexpr int E = 1 << EB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   typename S::L* lds = reinterpret_cast<typename S::L*>(smem_raw);
   double2* tab = reinterpret_cast<double2*>(smem_raw + (1u << a.g.tb) * S::kBytes);
   const uint32_t tid = threadIdx.x;
-  const uint64_t base = block_base(blockIdx.x, a.g);
+  const uint64_t base = block_base(xcd_block(blockIdx.x, gridDim.x), a.g);
   const uint32_t set = blockIdx.y;
   void* psi = reinterpret_cast<char*>(a.psi) + (uint64_t)set * a.set_stride_bytes;
   const LayerParams lp = layer_params(a, set, 0);
@@ -406,8 +425,10 @@ __global__ void __launch_bounds__(512, S::kMinWavesPerSimd) qaoa_sweep_kernel(co
   const int w_load = a.g.tb - EB;
   int w = w_load;
   // EXPV: the cost values are read with the state, in the coalesced load
-  // mapping, and the tile returns to that mapping for the reduction
-  typename D::RawT cv[EXPV ? E : 1];
+  // mapping, and the tile returns to that mapping for the reduction.  FUSE:
+  // they are read up front in the mapping the phase is applied in (the last
+  // window of the chunk order).
+  typename D::RawT cv[(EXPV || FUSE) ? E : 1];
   {
     const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g);
     if constexpr (INIT) {
@@ -417,16 +438,27 @@ __global__ void __launch_bounds__(512, S::kMinWavesPerSimd) qaoa_sweep_kernel(co
 #pragma unroll
       for (int k = 0; k < E; ++k) S::load(psi, xb + tile_off((uint32_t)k << w, a.g), vr[k], vi[k]);
     }
-    if constexpr (EXPV) {
-#pragma unroll
-      for (int k = 0; k < E; ++k) cv[k] = D::load_raw(a.diag, xb + tile_off((uint32_t)k << w, a.g));
-    }
   }
-  if constexpr (PHASE) apply_phase<S, D, EB>(vr, vi, a, lp, base, tid, w, tab);
+  if constexpr (EXPV) load_cost<D, EB>(cv, a, base, tid, w_load);
+  // complex64 tiles run at four waves per SIMD: their cost values are read
+  // when needed (holding them through the first gates would spill registers)
+  constexpr bool kEarlyCost = S::kMinWavesPerSimd <= 2;
+  if constexpr (FUSE && kEarlyCost) load_cost<D, EB>(cv, a, base, tid, a.g.chunk[a.g.nchunks - 1].w);
+  if constexpr (PHASE) {
+    typename D::RawT pc[E];
+    load_cost<D, EB>(pc, a, base, tid, w);
+    phase_from_raw<S, D, EB>(vr, vi, pc, a, lp, tid, tab);
+  }
   w = apply_mixer<S, EB>(vr, vi, lds, a.g, tid, w, lp.ca, lp.sb);
+  if constexpr (FUSE) {
+    const LayerParams lq = layer_params(a, set, 1);
+    if constexpr (!kEarlyCost) load_cost<D, EB>(cv, a, base, tid, w);
+    phase_from_raw<S, D, EB>(vr, vi, cv, a, lq, tid, tab);
+    w = apply_mixer<S, EB, true>(vr, vi, lds, a.g, tid, w, lq.ca, lq.sb);  // ends in the load mapping
+  }
 
   double e_part = 0.0, n_part = 0.0;
-  const int w_out = EXPV ? w_load : a.g.w_store;
+  const int w_out = EXPV ? w_load : (FUSE ? w : a.g.w_store);
   if (w != w_out) {
     exchange_c<S, EB>(vr, vi, lds, tid, w, w_out);
     w = w_out;
@@ -478,8 +510,12 @@ __global__ void __launch_bounds__(512) qaoa_tile_kernel(const SweepArgs a) {
     // the previous layer's table reads must finish before the table is restaged
     if (l > 0) __syncthreads();
     const LayerParams lp = layer_params(a, set, l);
-    apply_phase<S, D, EB>(vr, vi, a, lp, 0, tid, w, tab);
-    w = apply_mixer<S, EB>(vr, vi, lds, a.g, tid, w, lp.ca, lp.sb);
+    typename D::RawT pc[E];
+    load_cost<D, EB>(pc, a, 0, tid, w);
+    phase_from_raw<S, D, EB>(vr, vi, pc, a, lp, tid, tab);
+    // alternate the chunk order: each layer starts in the window the last one ended in
+    if (l & 1) w = apply_mixer<S, EB, true>(vr, vi, lds, a.g, tid, w, lp.ca, lp.sb);
+    else w = apply_mixer<S, EB>(vr, vi, lds, a.g, tid, w, lp.ca, lp.sb);
   }
   double e_part = 0.0, n_part = 0.0;
   if (a.flags & F_EXPV) expv_partials<D, EB>(vr, vi, a, 0, tid, w, e_part, n_part);
@@ -606,7 +642,7 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_kernel(const AdjArgs a) {
   typename S::L* lds = reinterpret_cast<typename S::L*>(smem_raw);
   double2* tab = reinterpret_cast<double2*>(smem_raw + (1u << a.g.tb) * S::kBytes);
   const uint32_t tid = threadIdx.x;
-  const uint64_t base = block_base(blockIdx.x, a.g);
+  const uint64_t base = block_base(xcd_block(blockIdx.x, gridDim.x), a.g);
   const size_t r = (size_t)a.layer;
   const LayerParams lp{a.pset[3 * r], a.pset[3 * r + 1], a.pset[3 * r + 2], a.ptab + r * kTabEntries};
   const int w_load = a.g.tb - EB;
@@ -781,7 +817,7 @@ __global__ void __launch_bounds__(512) fwht_sweep_kernel(const FwhtArgs a) {
   T* lds = reinterpret_cast<T*>(smem_raw);
   T* data = reinterpret_cast<T*>(a.data);
   const uint32_t tid = threadIdx.x;
-  const uint64_t base = block_base(blockIdx.x, a.g);
+  const uint64_t base = block_base(xcd_block(blockIdx.x, gridDim.x), a.g);
   R v[E];
   int w = a.g.tb - EB;
 #pragma unroll

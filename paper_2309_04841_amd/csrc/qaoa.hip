@@ -163,6 +163,32 @@ Plan make_plan(int n, size_t elem_bytes, int eb = kEB) {
 
 uint64_t plan_blocks(int n, const qk::TileGeom& g) { return (uint64_t)1 << (n - g.tb); }
 
+// Launch order of a multi-tile evaluation.  The mixer gates of a layer commute
+// (one gate per qubit), so layer l runs its sweeps in plan order when l is
+// even and in reverse order when l is odd.  The last sweep of layer l and the
+// first of layer l+1 then cover the same qubits and merge into one fused
+// launch: mixer gates of layer l, phase of layer l+1 (all of layer l is done
+// by then), mixer gates of layer l+1.  p layers of s sweeps take
+// 1 + (s-1) p launches instead of s p.
+struct SweepStep {
+  int sweep;  // index into Plan::sweeps
+  int layer;  // first layer this launch applies
+  int flags;  // qk::F_*
+};
+std::vector<SweepStep> sweep_schedule(int nsw, int p, bool init, bool expv) {
+  std::vector<SweepStep> out;
+  for (int l = 0; l < p; ++l) {
+    for (int i = (l == 0 ? 0 : 1); i < nsw; ++i) {  // position 0 of layer l > 0 ran fused
+      const int sw = (l & 1) ? nsw - 1 - i : i;
+      int flags = 0;
+      if (l == 0 && i == 0) flags |= qk::F_PHASE | (init ? qk::F_INIT : 0);
+      if (i == nsw - 1) flags |= (l + 1 < p) ? qk::F_FUSE : (expv ? qk::F_EXPV : 0);
+      out.push_back(SweepStep{sw, l, flags});
+    }
+  }
+  return out;
+}
+
 // Reverse (adjoint) sweeps hold two states per thread: 8 elements of each.
 constexpr int kEBAdj = 3;
 Plan adjoint_plan(int n, size_t state_bytes) { return make_plan(n, state_bytes, kEBAdj); }
@@ -181,21 +207,27 @@ size_t tile_lds_bytes(const qk::TileGeom& g, uint32_t threads, bool phase) {
   return std::max<size_t>(tile + tab, std::max<size_t>(16, 2 * threads) * sizeof(double));
 }
 
-template <class S, class D, bool INIT, bool PHASE, bool EXPV>
+template <class S, class D, bool INIT, bool PHASE, bool EXPV, bool FUSE = false>
 void launch_sweep_f(const qk::SweepArgs& a, uint64_t blocks, uint32_t sets, hipStream_t st) {
   const uint32_t threads = 1u << (a.g.tb - kEB);
-  const size_t lds = tile_lds_bytes<S, D>(a.g, threads, PHASE);
-  hipLaunchKernelGGL((qk::qaoa_sweep_kernel<S, D, kEB, INIT, PHASE, EXPV>), dim3((uint32_t)blocks, sets), dim3(threads),
-                     lds, st, a);
+  const size_t lds = tile_lds_bytes<S, D>(a.g, threads, PHASE || FUSE);
+  hipLaunchKernelGGL((qk::qaoa_sweep_kernel<S, D, kEB, INIT, PHASE, EXPV, FUSE>), dim3((uint32_t)blocks, sets),
+                     dim3(threads), lds, st, a);
 }
 
-// One sweep of one layer.  The plans only produce these flag combinations:
-// phase sweeps (first sweep of a layer, |+> generated in layer 1) and plain or
-// reducing mixer sweeps (the reduction in the last sweep of the last layer).
+// One sweep launch.  The schedules only produce these flag combinations: the
+// phase sweep that opens the first layer (|+> generated in registers when
+// init), plain mixer sweeps, fused sweeps (layer l's last sweep + layer l+1's
+// phase + the same qubits of layer l+1) and the reducing last sweep.
 template <class S, class D>
 int launch_sweep_d(const qk::SweepArgs& a, uint64_t blocks, uint32_t sets, hipStream_t st) {
   const bool init = a.flags & qk::F_INIT, phase = a.flags & qk::F_PHASE, expv = a.flags & qk::F_EXPV;
-  if (phase && !expv) {
+  const bool fuse = a.flags & qk::F_FUSE;
+  if (fuse) {
+    if (init || phase || expv)
+      return fail(QAOA_ERR_UNSUPPORTED, "internal: sweep flag combination %d not instantiated", a.flags);
+    launch_sweep_f<S, D, false, false, false, true>(a, blocks, sets, st);
+  } else if (phase && !expv) {
     if (init) launch_sweep_f<S, D, true, true, false>(a, blocks, sets, st);
     else launch_sweep_f<S, D, false, true, false>(a, blocks, sets, st);
   } else if (!init && !phase) {
@@ -412,8 +444,9 @@ constexpr size_t kStatWork = (3 * kStatBlocks + 4) * sizeof(int64_t);
 
 // Evolve workspace layout: [per-state (E, norm) partials of the last sweep]
 // [parameter rows: 3 doubles each][phase tables: kTabEntries double2 per row].
-// A single evaluation with host angles uses kMaxLayersPerLaunch rows (one
-// chunk of layers at a time); a batch with device angles uses batch * p rows.
+// A single evaluation with host angles uses kPrepRows rows (one chunk of
+// layers at a time, plus the next layer); a batch with device angles uses
+// batch * p rows.
 constexpr uint64_t kReduceChunks = 1024;  // stage-1 chunks of the two-stage reduction
 
 struct EvolveWork {
@@ -453,7 +486,7 @@ int enqueue_reduce(const double* partials, uint64_t count, uint64_t stride, uint
   LAUNCH_CHECK("finalize_batch_kernel");
   return QAOA_OK;
 }
-size_t evolve_work_bytes(int n, int state_dtype) { return evolve_work(n, 1, qk::kMaxLayersPerLaunch, state_dtype).total; }
+size_t evolve_work_bytes(int n, int state_dtype) { return evolve_work(n, 1, qk::kPrepRows, state_dtype).total; }
 size_t partials_bytes(int n, int state_dtype) { return evolve_work(n, 1, 0, state_dtype).partials_bytes; }
 
 // Gradient workspace: [forward evolve workspace][p parameter rows][p table rows]
@@ -706,7 +739,7 @@ static int enqueue_evolve(int n, int p, int batch, const double* h_gamma, const 
   const uint64_t N = (uint64_t)1 << n;
   const size_t S = state_elem_bytes(state_dtype);
   const bool host_angles = (h_gamma != nullptr);
-  const size_t rows = host_angles ? (size_t)qk::kMaxLayersPerLaunch : (size_t)batch * (size_t)p;
+  const size_t rows = host_angles ? (size_t)qk::kPrepRows : (size_t)batch * (size_t)p;
   const EvolveWork ew = evolve_work(n, (size_t)batch, rows, state_dtype);
   char* wk = reinterpret_cast<char*>(d_work);
   double* partials = reinterpret_cast<double*>(wk);
@@ -718,7 +751,7 @@ static int enqueue_evolve(int n, int p, int batch, const double* h_gamma, const 
   pa.pset = pset;
   pa.tab = use_tab ? tab : nullptr;
   pa.base = use_tab ? table_base(diag_dtype, diag_offset) : 0.0;
-  auto prep = [&](int l0, int nl) -> int {  // host angles, layers [l0, l0 + nl)
+  auto prep = [&](int l0, int nl) -> int {  // host angles, layers [l0, l0 + nl), nl <= kPrepRows
     pa.rows = nl;
     for (int i = 0; i < nl; ++i) { pa.gamma[i] = h_gamma[l0 + i]; pa.beta[i] = h_beta[l0 + i]; }
     hipLaunchKernelGGL(qk::layer_prep_kernel, dim3(nl), dim3(256), 0, st, pa);
@@ -740,9 +773,11 @@ static int enqueue_evolve(int n, int p, int batch, const double* h_gamma, const 
   a.amp0 = std::pow(2.0, -0.5 * n);
   a.ptab = tab;
   a.pset = pset;
-  a.p_total = host_angles ? qk::kMaxLayersPerLaunch : p;
+  a.p_total = host_angles ? qk::kPrepRows : p;
   a.set_stride_bytes = N * S;
   a.partials_stride = ew.partials_stride;
+  const std::vector<SweepStep> sched =
+      pl.single ? std::vector<SweepStep>() : sweep_schedule((int)pl.sweeps.size(), p, init != 0, d_out != nullptr);
   int rc = QAOA_OK;
   for (int s0 = 0; s0 < batch; s0 += G) {
     const uint32_t sets = (uint32_t)std::min(G, batch - s0);
@@ -750,10 +785,11 @@ static int enqueue_evolve(int n, int p, int batch, const double* h_gamma, const 
     a.psi = reinterpret_cast<char*>(d_states) + (size_t)s0 * N * S;
     a.partials = partials + (size_t)s0 * ew.partials_stride;
     uint64_t last_blocks = 1;
+    size_t next = 0;  // next schedule step
     for (int l0 = 0; l0 < p; l0 += qk::kMaxLayersPerLaunch) {
       const int nl = std::min(qk::kMaxLayersPerLaunch, p - l0);
       if (host_angles) {
-        rc = prep(l0, nl);
+        rc = prep(l0, std::min(nl + 1, p - l0));  // + the next layer, read by a fused sweep
         if (rc) return rc;
       }
       if (pl.single) {
@@ -765,20 +801,16 @@ static int enqueue_evolve(int n, int p, int batch, const double* h_gamma, const 
         LAUNCH_CHECK("qaoa_tile_kernel");
         continue;
       }
-      const size_t nsw = pl.sweeps.size();
       a.nlayers = 1;
-      for (int l = l0; l < l0 + nl; ++l) {
-        a.layer0 = host_angles ? l - l0 : l;
-        for (size_t sw = 0; sw < nsw; ++sw) {
-          a.g = pl.sweeps[sw];
-          const bool last = (l == p - 1) && (sw == nsw - 1);
-          a.flags = (sw == 0 ? qk::F_PHASE : 0) | ((sw == 0 && l == 0 && init) ? qk::F_INIT : 0) |
-                    ((last && d_out) ? qk::F_EXPV : 0);
-          last_blocks = plan_blocks(n, a.g);
-          rc = launch_sweep(a, state_dtype, diag_dtype, last_blocks, sets, st);
-          if (rc) return rc;
-          LAUNCH_CHECK("qaoa_sweep_kernel");
-        }
+      for (; next < sched.size() && sched[next].layer < l0 + nl; ++next) {
+        const SweepStep& stp = sched[next];
+        a.g = pl.sweeps[stp.sweep];
+        a.layer0 = host_angles ? stp.layer - l0 : stp.layer;
+        a.flags = stp.flags;
+        last_blocks = plan_blocks(n, a.g);
+        rc = launch_sweep(a, state_dtype, diag_dtype, last_blocks, sets, st);
+        if (rc) return rc;
+        LAUNCH_CHECK("qaoa_sweep_kernel");
       }
     }
     if (d_out) {
@@ -913,6 +945,22 @@ int qaoa_plan_describe(int kind, int n, int state_dtype, int elem_bytes, int* ou
   }
   if (out) for (int i = 0; i < (int)v.size() && i < cap; ++i) out[i] = v[i];
   return (int)v.size();
+}
+
+int qaoa_schedule_describe(int n, int p, int state_dtype, int init, int reduce, int* out, int cap) {
+  if (n < 1 || n > QAOA_MAX_QUBITS) return -fail(QAOA_ERR_INVALID, "n=%d out of range", n);
+  if (p < 0) return -fail(QAOA_ERR_INVALID, "p < 0");
+  if (!valid_state_dtype(state_dtype)) return -fail(QAOA_ERR_INVALID, "bad state dtype %d", state_dtype);
+  const Plan pl = make_plan(n, state_elem_bytes(state_dtype));
+  if (pl.single) return 0;
+  const std::vector<SweepStep> sched = sweep_schedule((int)pl.sweeps.size(), p, init != 0, reduce != 0);
+  int i = 0;
+  for (const auto& s : sched) {
+    const int v[3] = {s.sweep, s.layer, s.flags};
+    for (int j = 0; j < 3; ++j, ++i)
+      if (out && i < cap) out[i] = v[j];
+  }
+  return i;
 }
 
 int qaoa_grad_workspace_bytes(int n, int p, int state_dtype, int diag_dtype, size_t* bytes) {

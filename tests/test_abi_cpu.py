@@ -40,9 +40,10 @@ def test_version_and_last_error():
 
 
 def test_workspace_bytes():
-    # per-block (E, norm) partials of the last sweep + parameter rows and phase tables of 32 layers
-    # + the first stage of the two-stage reduction
-    assert _lib.workspace_bytes(_lib.QAOA_OP_EVOLVE, 26, _lib.QAOA_C128) == 16 * (1 << 14) + 3 * 8 * 32 + 32 * 512 * 16 + 16 * 1024
+    # per-block (E, norm) partials of the last sweep + parameter rows (256-byte aligned) and
+    # phase tables of 33 layers (a chunk of 32 and the next one) + the first stage of the
+    # two-stage reduction
+    assert _lib.workspace_bytes(_lib.QAOA_OP_EVOLVE, 26, _lib.QAOA_C128) == 16 * (1 << 14) + 1024 + 33 * 512 * 16 + 16 * 1024
     assert _lib.workspace_bytes(_lib.QAOA_OP_PRECOMPUTE, 20, diag_dtype=_lib.QAOA_DIAG_F64) == 0
     assert _lib.workspace_bytes(_lib.QAOA_OP_PRECOMPUTE, 20, diag_dtype=_lib.QAOA_DIAG_U16) >= 4 << 20
     with pytest.raises(_lib.QaoaError):
@@ -319,3 +320,55 @@ def test_server_validation():
     assert b"max_in_flight" in lib.qaoa_last_error()
     lib.qaoa_server_destroy.argtypes = [ctypes.c_void_p]
     assert lib.qaoa_server_destroy(None) == _lib.QAOA_ERR_INVALID
+
+
+def _sweep_qubits(s):
+    return {global_bit(s, t) for t in range(s["act_lo"], s["tb"])}
+
+
+@pytest.mark.parametrize("n,sdt", [(13, _lib.QAOA_C128), (20, _lib.QAOA_C128), (26, _lib.QAOA_C128),
+                                   (31, _lib.QAOA_C64), (34, _lib.QAOA_C64), (14, _lib.QAOA_C64)])
+@pytest.mark.parametrize("p", [1, 2, 3, 10, 33, 64])
+@pytest.mark.parametrize("init,reduce", [(True, True), (False, False)])
+def test_schedule_is_a_reordering_of_the_layers(n, sdt, p, init, reduce):
+    """Flattened, the launches must apply phase(l) then one gate per qubit of
+    layer l, for l = 0..p-1 in order; gates of one layer may come in any order
+    (they commute), nothing else may move (Sections 3.1-3.2)."""
+    plan = _lib.plan_describe(n, sdt)
+    sched = _lib.schedule_describe(n, p, sdt, init, reduce)
+    if plan["single"]:
+        assert sched == []
+        return
+    nsw = len(plan["sweeps"])
+    assert len(sched) == 1 + (nsw - 1) * p
+    ops = []
+    for i, (sw, layer, flags) in enumerate(sched):
+        qs = _sweep_qubits(plan["sweeps"][sw])
+        assert bool(flags & _lib.F_INIT) == (init and i == 0)
+        assert bool(flags & _lib.F_EXPV) == (reduce and i == len(sched) - 1)
+        assert not (flags & _lib.F_FUSE and flags & (_lib.F_PHASE | _lib.F_EXPV | _lib.F_INIT))
+        if flags & _lib.F_PHASE:
+            ops.append(("phase", layer))
+        ops += [("mix", layer, q) for q in qs]
+        if flags & _lib.F_FUSE:
+            assert layer + 1 < p
+            ops.append(("phase", layer + 1))
+            ops += [("mix", layer + 1, q) for q in qs]
+    # canonical grouping
+    pos = 0
+    for layer in range(p):
+        assert ops[pos] == ("phase", layer), (layer, ops[pos])
+        pos += 1
+        gates = ops[pos:pos + n]
+        assert sorted(gates) == [("mix", layer, q) for q in range(n)]
+        pos += n
+    assert pos == len(ops)
+
+
+def test_schedule_counts_and_fusion():
+    # LABS n=26 complex128, p=10: 3 sweeps per layer fused to 21 launches
+    sched = _lib.schedule_describe(26, 10, _lib.QAOA_C128)
+    assert len(sched) == 21
+    assert sum(1 for s in sched if s[2] & _lib.F_FUSE) == 9
+    with pytest.raises(_lib.QaoaError):
+        _lib.schedule_describe(0, 1)
