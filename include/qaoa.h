@@ -269,19 +269,24 @@ int qaoa_server_reset_stats(qaoa_server *s);
 int qaoa_plan_describe(int kind, int n, int state_dtype, int elem_bytes, int *out, int cap);
 
 /*
- * qaoa_schedule_describe -- diagnostic: the launch order of one qaoa_evolve /
- * qaoa_evolve_batch evaluation of p layers over the kind-0 plan (Sections
- * 3.1-3.2: each layer is the phase, then one mixer gate per qubit; the gates
- * of a layer commute, so the sweeps of odd layers run in reverse order and the
- * last sweep of layer l also applies layer l+1's phase and its gates on the
- * same qubits).  `init` and `reduce` as in qaoa_evolve (reduce = d_out given).
- * Writes up to `cap` ints, three per sweep launch: sweep index in the plan,
- * first layer applied, flags (1 generate |+>, 2 phase of that layer before the
- * gates, 4 emit (E, norm) partials, 8 fused with the next layer).  Returns the
- * number of ints needed (0 when the state is one tile and every layer runs in
- * one launch per 32 layers), or -QAOA_ERR_INVALID.
+ * qaoa_schedule_describe -- diagnostic: the launch order of one evaluation of
+ * p layers (Sections 3.1-3.2: each layer is the phase, then one mixer gate per
+ * qubit).  The gates of a layer commute, so the sweeps of alternate layers run
+ * in reverse order and the sweep that ends a layer also starts the next one on
+ * the same qubits.
+ * kind 0: qaoa_evolve / qaoa_evolve_batch over the kind-0 plan; `init` and
+ *   `reduce` as in qaoa_evolve (reduce = d_out given).  Flags: 1 generate |+>,
+ *   2 phase of that layer before its gates, 4 emit (E, norm) partials,
+ *   8 fused: then layer+1's phase and its gates on the same qubits.
+ * kind 1: the reverse pass of qaoa_grad over the kind-1 plan, layers p-1..0
+ *   (init, reduce ignored).  Flags: 1 lambda = c psi formed first, 2 undo of
+ *   that layer's phase after its gates, 8 fused: that phase undone, then
+ *   layer-1's gates on the same qubits.
+ * Writes up to `cap` ints, three per launch: sweep index in the plan, first
+ * layer applied, flags.  Returns the number of ints needed (0 when the state is
+ * one tile and a single launch runs the layers), or -QAOA_ERR_INVALID.
  */
-int qaoa_schedule_describe(int n, int p, int state_dtype, int init, int reduce, int *out, int cap);
+int qaoa_schedule_describe(int kind, int n, int p, int state_dtype, int init, int reduce, int *out, int cap);
 
 #ifdef __cplusplus
 }

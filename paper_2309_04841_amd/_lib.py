@@ -59,7 +59,7 @@ def _load() -> ctypes.CDLL:
     lib.qaoa_plan_describe.restype = I
     lib.qaoa_plan_describe.argtypes = [I, I, I, I, P, I]
     lib.qaoa_schedule_describe.restype = I
-    lib.qaoa_schedule_describe.argtypes = [I, I, I, I, I, P, I]
+    lib.qaoa_schedule_describe.argtypes = [I, I, I, I, I, I, P, I]
     lib.qaoa_grad_workspace_bytes.restype = I
     lib.qaoa_grad_workspace_bytes.argtypes = [I, I, I, I, ctypes.POINTER(SZ)]
     lib.qaoa_evolve_batch.restype = I
@@ -156,13 +156,19 @@ def plan_describe(n: int, state_dtype: int = QAOA_C128, elem_bytes: int = 0, kin
 F_INIT, F_PHASE, F_EXPV, F_FUSE = 1, 2, 4, 8
 
 
-def schedule_describe(n: int, p: int, state_dtype: int = QAOA_C128, init: bool = True, reduce: bool = True) -> list:
-    """Launch order of one evaluation: [(sweep, layer, flags)], empty for one-tile states."""
-    need = lib.qaoa_schedule_describe(n, p, state_dtype, int(init), int(reduce), None, 0)
+A_FIRST, A_PHASE, A_FUSE = 1, 2, 8
+SCHED_EVOLVE, SCHED_ADJOINT = 0, 1
+
+
+def schedule_describe(n: int, p: int, state_dtype: int = QAOA_C128, init: bool = True, reduce: bool = True,
+                      kind: int = SCHED_EVOLVE) -> list:
+    """Launch order of one evaluation (kind SCHED_EVOLVE) or of the gradient's
+    reverse pass (SCHED_ADJOINT): [(sweep, layer, flags)], empty for one-tile states."""
+    need = lib.qaoa_schedule_describe(kind, n, p, state_dtype, int(init), int(reduce), None, 0)
     if need < 0:
         check(-need)
     buf = (ctypes.c_int * max(need, 1))()
-    lib.qaoa_schedule_describe(n, p, state_dtype, int(init), int(reduce), buf, need)
+    lib.qaoa_schedule_describe(kind, n, p, state_dtype, int(init), int(reduce), buf, need)
     v = list(buf)[:need]
     return [tuple(v[i:i + 3]) for i in range(0, need, 3)]
 

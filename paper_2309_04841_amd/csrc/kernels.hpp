@@ -345,11 +345,16 @@ __device__ __forceinline__ void phase_from_raw(double (&vr)[1 << EB], double (&v
 
 // Stored cost values of the thread's register elements in window w.
 template <class D, int EB>
+__device__ __forceinline__ void load_cost_g(typename D::RawT (&cv)[1 << EB], const void* diag, uint64_t base,
+                                            uint32_t tid, int w, const TileGeom& g) {
+  const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), g);
+#pragma unroll
+  for (int k = 0; k < (1 << EB); ++k) cv[k] = D::load_raw(diag, xb + tile_off((uint32_t)k << w, g));
+}
+template <class D, int EB>
 __device__ __forceinline__ void load_cost(typename D::RawT (&cv)[1 << EB], const SweepArgs& a, uint64_t base,
                                           uint32_t tid, int w) {
-  const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g);
-#pragma unroll
-  for (int k = 0; k < (1 << EB); ++k) cv[k] = D::load_raw(a.diag, xb + tile_off((uint32_t)k << w, a.g));
+  load_cost_g<D, EB>(cv, a.diag, base, tid, w, a.g);
 }
 
 // Mixer gates of one layer on the tile's active qubits, window by window, in
@@ -538,7 +543,7 @@ __global__ void __launch_bounds__(512) qaoa_tile_kernel(const SweepArgs a) {
 // ----------------------------------------------------------------------------
 // reverse (adjoint) sweeps for the gradient
 // ----------------------------------------------------------------------------
-enum : int { A_FIRST = 1, A_PHASE = 2 };
+enum : int { A_FIRST = 1, A_PHASE = 2, A_FUSE = 8 };
 
 struct AdjArgs {
   void* psi;           // forward state, uncomputed in place
@@ -547,8 +552,9 @@ struct AdjArgs {
   const double2* ptab; // phase tables, kTabEntries per layer row
   const double* pset;  // rows (gamma, cos beta, sin beta)
   double* partials;    // this launch's (beta term, gamma term) per block
+  double* partials2;   // A_FUSE: the beta term of layer - 1 per block (gamma term 0)
   double diag_offset;
-  int layer;           // row of pset / ptab
+  int layer;           // row of pset / ptab (the layer undone first)
   int nlayers;         // whole-state tile kernel: layers [0, nlayers) in reverse
   uint64_t layer_partials_stride;  // tile kernel: doubles between layers' partials
   TileGeom g;
@@ -563,13 +569,13 @@ __device__ __forceinline__ double xterm(double pr0, double pi0, double pr1, doub
 // Undo the layer's mixer gates on the tile's active qubits for psi and lambda
 // (gate with -beta), accumulating Im<lambda|X_q|psi> per undone qubit (X_q
 // commutes with every mixer gate, so any point of the undo gives the same value).
-template <class S, int EB>
+template <class S, int EB, bool REV = false>
 __device__ __forceinline__ int undo_mixer(double (&vr)[1 << EB], double (&vi)[1 << EB], double (&lr)[1 << EB],
                                           double (&li)[1 << EB], typename S::L* lds, const TileGeom& g,
                                           uint32_t tid, int w, double ca, double sb, double& xacc) {
   constexpr int E = 1 << EB;
-  for (int ci = 0; ci < g.nchunks; ++ci) {
-    const Chunk ch = g.chunk[ci];
+  for (int i = 0; i < g.nchunks; ++i) {
+    const Chunk ch = g.chunk[REV ? g.nchunks - 1 - i : i];
     if (ch.w != w) {
       exchange_c<S, EB>(vr, vi, lds, tid, w, ch.w);
       exchange_c<S, EB>(lr, li, lds, tid, w, ch.w);
@@ -614,13 +620,18 @@ __device__ __forceinline__ void undo_phase(double (&vr)[1 << EB], double (&vi)[1
     fast = !__syncthreads_or(!ok);
   }
   if (fast) {
+    // groups of four elements bound the table entries in flight (registers)
 #pragma unroll
-    for (int k = 0; k < E; ++k) {
-      const int32_t u = D::tab_index(cv[k]);
-      const double2 h = tab[u >> 8], lo = tab[256 + (u & 255)];
-      const double fr = fma(h.x, lo.x, -h.y * lo.y), fi = -fma(h.x, lo.y, h.y * lo.x);  // conjugate
-      cmul_inplace(vr[k], vi[k], fr, fi);
-      cmul_inplace(lr[k], li[k], fr, fi);
+    for (int k0 = 0; k0 < E; k0 += 4) {
+#pragma unroll
+      for (int k = k0; k < k0 + 4 && k < E; ++k) {
+        const int32_t u = D::tab_index(cv[k]);
+        const double2 h = tab[u >> 8], lo = tab[256 + (u & 255)];
+        const double fr = fma(h.x, lo.x, -h.y * lo.y), fi = -fma(h.x, lo.y, h.y * lo.x);  // conjugate
+        cmul_inplace(vr[k], vi[k], fr, fi);
+        cmul_inplace(lr[k], li[k], fr, fi);
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
   } else {
 #pragma unroll
@@ -632,10 +643,13 @@ __device__ __forceinline__ void undo_phase(double (&vr)[1 << EB], double (&vi)[1
   }
 }
 
-// One reverse sweep of one layer (multi-tile states):
+// One reverse sweep (multi-tile states):
 //   FIRST  lambda = c * psi from the loaded psi (lambda is only written)
-//   PHASE  after the mixer undo: gamma term and phase undo (first sweep of the layer)
-template <class S, class D, int EB, bool FIRST, bool PHASE>
+//   PHASE  after the mixer undo: gamma term and phase undo (last sweep of the layer)
+//   FUSE   the tile's gates of layer l undone, then layer l's gamma term and
+//          phase undo (every other gate of layer l is undone by then), then
+//          the tile's gates of layer l-1 undone
+template <class S, class D, int EB, bool FIRST, bool PHASE, bool FUSE>
 __global__ void __launch_bounds__(512) qaoa_adjoint_kernel(const AdjArgs a) {
   constexpr int E = 1 << EB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -648,15 +662,12 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_kernel(const AdjArgs a) {
   const int w_load = a.g.tb - EB;
   int w = w_load;
   double vr[E], vi[E], lr[E], li[E];
-  typename D::RawT cv[(FIRST || PHASE) ? E : 1];
+  typename D::RawT cv[(FIRST || PHASE || FUSE) ? E : 1];
   {
     const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g);
 #pragma unroll
     for (int k = 0; k < E; ++k) S::load(a.psi, xb + tile_off((uint32_t)k << w, a.g), vr[k], vi[k]);
-    if constexpr (FIRST || PHASE) {
-#pragma unroll
-      for (int k = 0; k < E; ++k) cv[k] = D::load_raw(a.diag, xb + tile_off((uint32_t)k << w, a.g));
-    }
+    if constexpr (FIRST || PHASE) load_cost_g<D, EB>(cv, a.diag, base, tid, w, a.g);
     if constexpr (FIRST) {
 #pragma unroll
       for (int k = 0; k < E; ++k) {
@@ -668,10 +679,18 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_kernel(const AdjArgs a) {
 #pragma unroll
       for (int k = 0; k < E; ++k) S::load(a.lam, xb + tile_off((uint32_t)k << w, a.g), lr[k], li[k]);
     }
+    // FUSE: cost values in the mapping of the last chunk's window, where the
+    // phase is undone
+    if constexpr (FUSE) load_cost_g<D, EB>(cv, a.diag, base, tid, a.g.chunk[a.g.nchunks - 1].w, a.g);
   }
-  double xacc = 0.0, gacc = 0.0;
+  double xacc = 0.0, gacc = 0.0, xacc2 = 0.0;
   w = undo_mixer<S, EB>(vr, vi, lr, li, lds, a.g, tid, w, lp.ca, lp.sb, xacc);
-  const int w_out = PHASE ? w_load : a.g.w_store;
+  if constexpr (FUSE) {
+    undo_phase<D, EB>(vr, vi, lr, li, cv, a, lp, tab, tid, gacc);
+    const size_t r1 = r - 1;
+    w = undo_mixer<S, EB, true>(vr, vi, lr, li, lds, a.g, tid, w, a.pset[3 * r1 + 1], a.pset[3 * r1 + 2], xacc2);
+  }
+  const int w_out = PHASE ? w_load : (FUSE ? w : a.g.w_store);
   if (w != w_out) {
     exchange_c<S, EB>(vr, vi, lds, tid, w, w_out);
     exchange_c<S, EB>(lr, li, lds, tid, w, w_out);
@@ -692,6 +711,14 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_kernel(const AdjArgs a) {
   if (tid == 0) {
     a.partials[2 * (uint64_t)blockIdx.x] = xacc;
     a.partials[2 * (uint64_t)blockIdx.x + 1] = gacc;
+  }
+  if constexpr (FUSE) {
+    double zero = 0.0;
+    block_sum2(xacc2, zero, reinterpret_cast<double*>(smem_raw));
+    if (tid == 0) {
+      a.partials2[2 * (uint64_t)blockIdx.x] = xacc2;
+      a.partials2[2 * (uint64_t)blockIdx.x + 1] = 0.0;
+    }
   }
 }
 
@@ -752,10 +779,11 @@ __global__ void __launch_bounds__(256) grad_finalize_kernel(const double* partia
   const int l = blockIdx.x;
   const double* part = partials + (uint64_t)l * layer_stride;
   double xb = 0.0, gg = 0.0;
+  // the gamma term is nonzero only in the sweep that undid the layer's phase
   for (int s = 0; s < nsw; ++s)
     for (uint64_t i = threadIdx.x; i < blocks; i += blockDim.x) {
       xb += part[2 * (s * blocks + i)];
-      if (s == 0) gg += part[2 * i + 1];
+      gg += part[2 * (s * blocks + i) + 1];
     }
   block_sum2(xb, gg, scratch);
   if (threadIdx.x == 0) {

@@ -175,6 +175,25 @@ struct SweepStep {
   int layer;  // first layer this launch applies
   int flags;  // qk::F_*
 };
+// Reverse pass of the gradient: layers p-1 .. 0, each run with alternating
+// sweep order; the last sweep of layer l > 0 also undoes layer l's phase (all
+// of layer l's gates are undone by then) and layer l-1's gates on the same
+// qubits.  `layer` is the layer undone first; flags are qk::A_*.
+std::vector<SweepStep> adjoint_schedule(int nsw, int p) {
+  std::vector<SweepStep> out;
+  for (int l = p - 1; l >= 0; --l) {
+    const int r = p - 1 - l;
+    for (int i = (l == p - 1 ? 0 : 1); i < nsw; ++i) {  // position 0 of layer l < p-1 ran fused
+      const int sw = (r & 1) ? i : nsw - 1 - i;
+      int flags = 0;
+      if (l == p - 1 && i == 0) flags |= qk::A_FIRST;
+      if (i == nsw - 1) flags |= (l > 0) ? qk::A_FUSE : qk::A_PHASE;
+      out.push_back(SweepStep{sw, l, flags});
+    }
+  }
+  return out;
+}
+
 std::vector<SweepStep> sweep_schedule(int nsw, int p, bool init, bool expv) {
   std::vector<SweepStep> out;
   for (int l = 0; l < p; ++l) {
@@ -287,21 +306,24 @@ void launch_tile(const qk::SweepArgs& a, int state_dtype, int diag_dtype, int eb
   else launch_tile_s<qk::C64>(a, diag_dtype, eb, sets, st);
 }
 
-template <class S, class D, bool FIRST, bool PHASE>
+template <class S, class D, bool FIRST, bool PHASE, bool FUSE>
 void launch_adj_f(const qk::AdjArgs& a, uint64_t blocks, hipStream_t st) {
   const uint32_t threads = 1u << (a.g.tb - kEBAdj);
   const size_t tile = ((size_t)1 << a.g.tb) * S::kBytes;
   const size_t lds = std::max<size_t>(tile + qk::kTabEntries * sizeof(double2), std::max<size_t>(16, 2 * threads) * sizeof(double));
-  hipLaunchKernelGGL((qk::qaoa_adjoint_kernel<S, D, kEBAdj, FIRST, PHASE>), dim3((uint32_t)blocks), dim3(threads), lds,
-                     st, a);
+  hipLaunchKernelGGL((qk::qaoa_adjoint_kernel<S, D, kEBAdj, FIRST, PHASE, FUSE>), dim3((uint32_t)blocks),
+                     dim3(threads), lds, st, a);
 }
 
 template <class S, class D>
-int launch_adj_d(const qk::AdjArgs& a, bool first, bool phase, uint64_t blocks, hipStream_t st) {
-  if (first && !phase) launch_adj_f<S, D, true, false>(a, blocks, st);
-  else if (!first && phase) launch_adj_f<S, D, false, true>(a, blocks, st);
-  else if (!first && !phase) launch_adj_f<S, D, false, false>(a, blocks, st);
-  else return fail(QAOA_ERR_UNSUPPORTED, "internal: adjoint flag combination not instantiated");
+int launch_adj_d(const qk::AdjArgs& a, int flags, uint64_t blocks, hipStream_t st) {
+  switch (flags) {
+    case qk::A_FIRST: launch_adj_f<S, D, true, false, false>(a, blocks, st); break;
+    case qk::A_PHASE: launch_adj_f<S, D, false, true, false>(a, blocks, st); break;
+    case qk::A_FUSE: launch_adj_f<S, D, false, false, true>(a, blocks, st); break;
+    case 0: launch_adj_f<S, D, false, false, false>(a, blocks, st); break;
+    default: return fail(QAOA_ERR_UNSUPPORTED, "internal: adjoint flag combination %d not instantiated", flags);
+  }
   return QAOA_OK;
 }
 
@@ -324,25 +346,24 @@ void launch_adj_tile_d(const qk::AdjArgs& a, int eb, hipStream_t st) {
 
 // Reverse sweep (tile == false) or whole-state reverse pass (tile == true).
 template <class S>
-int launch_adj_s(const qk::AdjArgs& a, int ddt, bool tile, int eb, bool first, bool phase, uint64_t blocks,
-                 hipStream_t st) {
+int launch_adj_s(const qk::AdjArgs& a, int ddt, bool tile, int eb, int flags, uint64_t blocks, hipStream_t st) {
   switch (ddt) {
     case QAOA_DIAG_I32:
       if (tile) { launch_adj_tile_d<S, qk::DI32>(a, eb, st); return QAOA_OK; }
-      return launch_adj_d<S, qk::DI32>(a, first, phase, blocks, st);
+      return launch_adj_d<S, qk::DI32>(a, flags, blocks, st);
     case QAOA_DIAG_U16:
       if (tile) { launch_adj_tile_d<S, qk::DU16>(a, eb, st); return QAOA_OK; }
-      return launch_adj_d<S, qk::DU16>(a, first, phase, blocks, st);
+      return launch_adj_d<S, qk::DU16>(a, flags, blocks, st);
     default:
       if (tile) { launch_adj_tile_d<S, qk::DF64>(a, eb, st); return QAOA_OK; }
-      return launch_adj_d<S, qk::DF64>(a, first, phase, blocks, st);
+      return launch_adj_d<S, qk::DF64>(a, flags, blocks, st);
   }
 }
 
-int launch_adj(const qk::AdjArgs& a, int sdt, int ddt, bool tile, int eb, bool first, bool phase, uint64_t blocks,
-               hipStream_t st) {
-  if (sdt == QAOA_C128) return launch_adj_s<qk::C128>(a, ddt, tile, eb, first, phase, blocks, st);
-  return launch_adj_s<qk::C64>(a, ddt, tile, eb, first, phase, blocks, st);
+// Reverse sweep with qk::A_* flags (tile == false) or whole-state reverse pass (tile == true).
+int launch_adj(const qk::AdjArgs& a, int sdt, int ddt, bool tile, int eb, int flags, uint64_t blocks, hipStream_t st) {
+  if (sdt == QAOA_C128) return launch_adj_s<qk::C128>(a, ddt, tile, eb, flags, blocks, st);
+  return launch_adj_s<qk::C64>(a, ddt, tile, eb, flags, blocks, st);
 }
 
 template <class S, class D>
@@ -947,13 +968,16 @@ int qaoa_plan_describe(int kind, int n, int state_dtype, int elem_bytes, int* ou
   return (int)v.size();
 }
 
-int qaoa_schedule_describe(int n, int p, int state_dtype, int init, int reduce, int* out, int cap) {
+int qaoa_schedule_describe(int kind, int n, int p, int state_dtype, int init, int reduce, int* out, int cap) {
+  if (kind != 0 && kind != 1) return -fail(QAOA_ERR_INVALID, "bad schedule kind %d", kind);
   if (n < 1 || n > QAOA_MAX_QUBITS) return -fail(QAOA_ERR_INVALID, "n=%d out of range", n);
   if (p < 0) return -fail(QAOA_ERR_INVALID, "p < 0");
   if (!valid_state_dtype(state_dtype)) return -fail(QAOA_ERR_INVALID, "bad state dtype %d", state_dtype);
-  const Plan pl = make_plan(n, state_elem_bytes(state_dtype));
+  const size_t S = state_elem_bytes(state_dtype);
+  const Plan pl = kind == 0 ? make_plan(n, S) : adjoint_plan(n, S);
   if (pl.single) return 0;
-  const std::vector<SweepStep> sched = sweep_schedule((int)pl.sweeps.size(), p, init != 0, reduce != 0);
+  const std::vector<SweepStep> sched = kind == 0 ? sweep_schedule((int)pl.sweeps.size(), p, init != 0, reduce != 0)
+                                                 : adjoint_schedule((int)pl.sweeps.size(), p);
   int i = 0;
   for (const auto& s : sched) {
     const int v[3] = {s.sweep, s.layer, s.flags};
@@ -1025,21 +1049,20 @@ int qaoa_grad(int n, int p, const double* gamma, const double* beta, const void*
     a.nlayers = p;
     a.partials = rev;
     a.layer_partials_stride = gw.layer_stride;
-    rc = launch_adj(a, state_dtype, diag_dtype, true, pl.eb, true, true, 1, st);
+    rc = launch_adj(a, state_dtype, diag_dtype, true, pl.eb, 0, 1, st);
     if (rc) return rc;
     LAUNCH_CHECK("qaoa_adjoint_tile_kernel");
   } else {
     blocks = plan_blocks(n, pl.sweeps[0]);
-    for (int l = p - 1; l >= 0; --l) {
-      a.layer = l;
-      for (int sw = nsw - 1; sw >= 0; --sw) {
-        a.g = pl.sweeps[sw];
-        a.partials = rev + (size_t)l * gw.layer_stride + (size_t)sw * blocks * 2;
-        const bool first = (l == p - 1) && (sw == nsw - 1);
-        rc = launch_adj(a, state_dtype, diag_dtype, false, kEBAdj, first, sw == 0, blocks, st);
-        if (rc) return rc;
-        LAUNCH_CHECK("qaoa_adjoint_kernel");
-      }
+    auto slot = [&](int l, int sw) { return rev + (size_t)l * gw.layer_stride + (size_t)sw * blocks * 2; };
+    for (const SweepStep& stp : adjoint_schedule(nsw, p)) {
+      a.layer = stp.layer;
+      a.g = pl.sweeps[stp.sweep];
+      a.partials = slot(stp.layer, stp.sweep);
+      a.partials2 = (stp.flags & qk::A_FUSE) ? slot(stp.layer - 1, stp.sweep) : nullptr;
+      rc = launch_adj(a, state_dtype, diag_dtype, false, kEBAdj, stp.flags, blocks, st);
+      if (rc) return rc;
+      LAUNCH_CHECK("qaoa_adjoint_kernel");
     }
   }
   hipLaunchKernelGGL(qk::grad_finalize_kernel, dim3(p), dim3(256), 0, st, (const double*)rev, p, nsw, blocks,

@@ -372,3 +372,44 @@ def test_schedule_counts_and_fusion():
     assert sum(1 for s in sched if s[2] & _lib.F_FUSE) == 9
     with pytest.raises(_lib.QaoaError):
         _lib.schedule_describe(0, 1)
+    with pytest.raises(_lib.QaoaError):
+        _lib.schedule_describe(20, 1, kind=2)
+
+
+@pytest.mark.parametrize("n,sdt", [(12, _lib.QAOA_C128), (18, _lib.QAOA_C128), (26, _lib.QAOA_C128),
+                                   (31, _lib.QAOA_C64), (16, _lib.QAOA_C64)])
+@pytest.mark.parametrize("p", [1, 2, 3, 10, 40])
+def test_adjoint_schedule_undoes_layers_in_reverse(n, sdt, p):
+    """Flattened, the reverse pass must undo, for l = p-1 .. 0, one gate per
+    qubit of layer l (any order) and then layer l's phase; lambda = c psi is
+    formed by the first launch only; every (layer, sweep) partial slot is
+    written exactly once, and the gamma term of layer l by the launch that
+    undoes its phase."""
+    plan = _lib.plan_describe(n, sdt, kind=_lib.PLAN_ADJOINT)
+    sched = _lib.schedule_describe(n, p, sdt, kind=_lib.SCHED_ADJOINT)
+    if plan["single"]:
+        assert sched == []
+        return
+    nsw = len(plan["sweeps"])
+    assert len(sched) == 1 + (nsw - 1) * p
+    ops, slots = [], []
+    for i, (sw, layer, flags) in enumerate(sched):
+        qs = _sweep_qubits(plan["sweeps"][sw])
+        assert bool(flags & _lib.A_FIRST) == (i == 0)
+        assert flags in (0, _lib.A_FIRST, _lib.A_PHASE, _lib.A_FUSE)
+        ops += [("undo", layer, q) for q in qs]
+        slots.append((layer, sw))
+        if flags & (_lib.A_PHASE | _lib.A_FUSE):
+            ops.append(("unphase", layer))
+        if flags & _lib.A_FUSE:
+            assert layer >= 1
+            ops += [("undo", layer - 1, q) for q in qs]
+            slots.append((layer - 1, sw))
+    assert sorted(slots) == [(l, s) for l in range(p) for s in range(nsw)]
+    pos = 0
+    for layer in range(p - 1, -1, -1):
+        assert sorted(ops[pos:pos + n]) == [("undo", layer, q) for q in range(n)]
+        pos += n
+        assert ops[pos] == ("unphase", layer)
+        pos += 1
+    assert pos == len(ops)
