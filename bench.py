@@ -32,27 +32,23 @@ CONFIGS = {
 }
 
 
-def _sweep_bytes(plan, n, p, state_bytes, diag_bytes, fused_e=True):
-    """Algorithmic HBM bytes of one evaluation, split per sweep launch.
+def _sweep_bytes(sched, n, state_bytes, diag_bytes):
+    """Algorithmic HBM bytes of one evaluation, per sweep launch of its schedule.
 
-    Per layer every sweep reads and writes the state once (S bytes each way per
-    element); the first sweep also reads the cost vector (D).  Layer 1 does not
-    read the state (|+> is generated in registers).  The E reduction is fused
-    into the last sweep and re-reads the cost vector there.
+    Every launch reads and writes the state once (S bytes each way per element),
+    except the first, which generates |+> in registers and only writes.  A
+    launch that applies a phase (the opening sweep, and each fused sweep that
+    joins two layers) reads the cost vector (D bytes per element); so does the
+    last launch, which reduces E.
     """
+    from paper_2309_04841_amd import _lib
     N = 1 << n
     per_launch = []
-    nsw = len(plan["sweeps"])
-    for l in range(p):
-        for s in range(nsw):
-            b = 2 * state_bytes * N
-            if s == 0:
-                b += diag_bytes * N
-                if l == 0:
-                    b -= state_bytes * N
-            if fused_e and l == p - 1 and s == nsw - 1:
-                b += diag_bytes * N
-            per_launch.append(b)
+    for _sw, _layer, flags in sched:
+        b = (1 if flags & _lib.F_INIT else 2) * state_bytes * N
+        if flags & (_lib.F_PHASE | _lib.F_FUSE | _lib.F_EXPV):
+            b += diag_bytes * N
+        per_launch.append(b)
     return per_launch
 
 
@@ -130,8 +126,7 @@ def bench_batch(args):
         q.qaoa_evolve(n, gam[s], bet[s], diag, psi, diag_offset=off, out=o1, work=w1)
     torch.cuda.synchronize()
     t_single = time.perf_counter() - t0
-    N = 1 << n
-    bytes_per_set = (p * (2 * 2 * 8 + 4) + 4 - 8) * N  # 2 sweeps per layer at n=22 complex64
+    bytes_per_set = sum(_sweep_bytes(_lib.schedule_describe(n, p, _lib.QAOA_C64), n, 8, 4))
     return {"metric": "batched QAOA evals/s, weighted MaxCut G(22,0.3) p=6, 512 sets", "value": batch / t_batch,
             "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": 1e3 * t_batch, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
@@ -275,7 +270,7 @@ def main(argv=None):
     def step():
         q.qaoa_evolve(n, gamma, beta, diag, psi, init=True, diag_offset=off, out=out, work=work)
 
-    for _ in range(args.warmup):
+    for _ in range(max(1, args.warmup)):  # at least one evaluation, the reference for reproducibility
         step()
     torch.cuda.synchronize()
     e_first = out.cpu().numpy().copy()
@@ -297,7 +292,8 @@ def main(argv=None):
         return 1
 
     plan = _lib.plan_describe(n, _lib.state_dtype_code(psi))
-    per_launch = _sweep_bytes(plan, n, p, S, D)
+    sched = _lib.schedule_describe(n, p, _lib.state_dtype_code(psi))
+    per_launch = _sweep_bytes(sched, n, S, D)
     launches = len(per_launch)
     bytes_per_eval = float(sum(per_launch))
     # the timed region holds `launches` sweep launches and one tiny finalize
@@ -311,7 +307,7 @@ def main(argv=None):
         "unit": "evals/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": args.warmup,
+        "warmup": max(1, args.warmup),
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",
