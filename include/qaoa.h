@@ -259,7 +259,9 @@ int qaoa_server_reset_stats(qaoa_server *s);
  * kind 2: the cost-vector transform for elements of elem_bytes (2, 4 or 8).
  * Writes up to `cap` ints:
  *   [0] number of sweeps S, [1] register bits per thread EB, [2] 1 if the whole
- *   vector is one tile (all layers in one launch), then per sweep:
+ *   vector is one tile (all layers in one launch), [3] 1 if complex128 tiles
+ *   exceed the LDS (up to 2^14 elements, 1024 threads; window changes move real
+ *   and imaginary parts separately as 8-byte entries), then per sweep:
  *   tb, R, hA, qA, qB, act_lo, w_store, nchunks, and nchunks triples (w, jlo, jhi).
  * Tile bits [0,R) are global bits [0,R); tile bits [R,R+hA) are global bits
  * [qA,qA+hA); tile bits [R+hA,tb) are global bits [qB,qB+tb-R-hA); tile bits

@@ -131,7 +131,7 @@ PLAN_EVOLVE, PLAN_ADJOINT, PLAN_TRANSFORM = 0, 1, 2
 
 
 def plan_describe(n: int, state_dtype: int = QAOA_C128, elem_bytes: int = 0, kind: int | None = None) -> dict:
-    """The sweep plan as a dict: {'eb', 'single', 'sweeps': [{'tb','R','hA','qA','qB','act_lo','w_store','chunks'}]}.
+    """The sweep plan as a dict: {'eb', 'single', 'wide', 'sweeps': [{'tb','R','hA','qA','qB','act_lo','w_store','chunks'}]}.
     kind: PLAN_EVOLVE (default), PLAN_ADJOINT, or PLAN_TRANSFORM (elem_bytes)."""
     if kind is None:
         kind = PLAN_TRANSFORM if state_dtype < 0 else PLAN_EVOLVE
@@ -141,8 +141,8 @@ def plan_describe(n: int, state_dtype: int = QAOA_C128, elem_bytes: int = 0, kin
     buf = (ctypes.c_int * need)()
     lib.qaoa_plan_describe(kind, n, state_dtype, elem_bytes, buf, need)
     v = list(buf)
-    ns, eb, single = v[0], v[1], v[2]
-    i = 3
+    ns, eb, single, wide = v[0], v[1], v[2], v[3]
+    i = 4
     sweeps = []
     for _ in range(ns):
         tb, R, hA, qA, qB, act_lo, ws, nc = v[i:i + 8]
@@ -150,7 +150,7 @@ def plan_describe(n: int, state_dtype: int = QAOA_C128, elem_bytes: int = 0, kin
         chunks = [tuple(v[i + 3 * c:i + 3 * c + 3]) for c in range(nc)]
         i += 3 * nc
         sweeps.append(dict(tb=tb, R=R, hA=hA, qA=qA, qB=qB, act_lo=act_lo, w_store=ws, chunks=chunks))
-    return dict(eb=eb, single=bool(single), sweeps=sweeps)
+    return dict(eb=eb, single=bool(single), wide=bool(wide), sweeps=sweeps)
 
 
 F_INIT, F_PHASE, F_EXPV, F_FUSE = 1, 2, 4, 8

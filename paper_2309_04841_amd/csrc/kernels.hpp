@@ -41,6 +41,9 @@ typedef float fvec2 __attribute__((ext_vector_type(2)));
 struct C128 {  // complex128: (double re, double im)
   using L = double2;
   static constexpr int kBytes = 16;
+  static constexpr int kLdsBytes = 16;   // LDS bytes per tile element
+  static constexpr bool kSplit = false;  // exchanges move whole elements
+  static constexpr int kMaxThreads = 512;
   // 64 KiB tiles + tables: two workgroups per CU by LDS, two waves per SIMD
   static constexpr int kMinWavesPerSimd = 2;
   __device__ static __forceinline__ void load(const void* p, uint64_t x, double& r, double& i) {
@@ -61,6 +64,9 @@ struct C128 {  // complex128: (double re, double im)
 struct C64 {  // complex64 storage, FP64 arithmetic in registers
   using L = float2;
   static constexpr int kBytes = 8;
+  static constexpr int kLdsBytes = 8;
+  static constexpr bool kSplit = false;
+  static constexpr int kMaxThreads = 512;
   // 512-thread tiles: four waves per SIMD keep two workgroups resident per CU
   static constexpr int kMinWavesPerSimd = 4;
   __device__ static __forceinline__ void load(const void* p, uint64_t x, double& r, double& i) {
@@ -78,6 +84,17 @@ struct C64 {  // complex64 storage, FP64 arithmetic in registers
     const float2 v = s[pos];
     r = (double)v.x; i = (double)v.y;
   }
+};
+
+// complex128 in tiles of up to 2^14 elements (256 KiB, more than the LDS):
+// 1024 threads of 16 elements; a window change moves the real parts, then the
+// imaginary parts, through one 128 KiB buffer of doubles.  Used when the larger
+// tile saves a sweep per layer.
+struct C128W : C128 {
+  static constexpr int kLdsBytes = 8;
+  static constexpr bool kSplit = true;
+  static constexpr int kMaxThreads = 1024;
+  static constexpr int kMinWavesPerSimd = 4;  // one 16-wave workgroup per CU
 };
 
 // Cost-vector policies.  `get` returns the stored value as a double (the
@@ -100,6 +117,7 @@ struct DI32 {
     return u < 65536u ? (int32_t)u : -1;
   }
   static constexpr double kTableBase = -32768.0;
+  static constexpr int kTabLds = 512;  // LDS entries: HI|LO, F1|LO or F3|F2
   using RawT = int32_t;
   __device__ static __forceinline__ double value(RawT r) { return (double)r; }
 };
@@ -115,6 +133,7 @@ struct DU16 {
   }
   __device__ static __forceinline__ int32_t tab_index(int32_t v) { return v; }
   static constexpr double kTableBase = 0.0;
+  static constexpr int kTabLds = 512;
   using RawT = int32_t;
   __device__ static __forceinline__ double value(RawT r) { return (double)r; }
 };
@@ -128,6 +147,7 @@ struct DF64 {
   __device__ static __forceinline__ int32_t raw(const void*, uint64_t) { return 0; }
   __device__ static __forceinline__ int32_t tab_index(int32_t) { return -1; }
   static constexpr double kTableBase = 0.0;
+  static constexpr int kTabLds = 0;
   using RawT = double;
   __device__ static __forceinline__ double value(RawT r) { return r; }
 };
@@ -137,7 +157,14 @@ struct DF64 {
 //   exp(-i g c) = HI[u >> 8] * LO[u & 255],
 //   HI[m] = exp(-i g (256 m + base + offset)),  LO[j] = exp(-i g j),
 // each entry from one sincos of an exactly representable integer times g.
-constexpr int kTabEntries = 512;  // HI (256) then LO (256), double2 (cos, -sin)
+// int32 values outside that range use the bytes b0..b3 of the stored value v
+// (two's complement, b3 signed), in two passes of the same two-table product:
+//   exp(-i g (v + offset)) = (F1[b1] * LO[b0]) * (F3[b3] * F2[b2]),
+//   F1[m] = exp(-i g 256 m),  F2[m] = exp(-i g 65536 m),
+//   F3[m] = exp(-i g (2^24 s(m) + offset)),  s(m) = m - 256 [m >= 128].
+// A layer's row holds HI, LO, F1, F2, F3 (256 double2 (cos, -sin) each).
+constexpr int kTabEntries = 512;  // HI then LO: the part staged for in-range values
+constexpr int kTabRow = 1280;     // row stride: HI, LO, F1, F2, F3
 
 // Per-layer parameters, computed on the device for every path so that batched
 // and single evaluations use bit-identical values: row r gets
@@ -150,6 +177,7 @@ struct PrepArgs {
   double* pset;
   double2* tab;
   double base;   // table base + cost offset
+  double off;    // cost offset
   int rows;
   double gamma[kPrepRows];
   double beta[kPrepRows];
@@ -168,11 +196,19 @@ __global__ void __launch_bounds__(256) layer_prep_kernel(const PrepArgs a) {
     a.pset[3 * r + 2] = sb;
   }
   if (a.tab != nullptr) {
-    for (int e = threadIdx.x; e < kTabEntries; e += blockDim.x) {
-      const double v = e < 256 ? 256.0 * (double)e + a.base : (double)(e - 256);
+    for (int e = threadIdx.x; e < kTabRow; e += blockDim.x) {
+      const int m = e & 255;
+      double v;
+      switch (e >> 8) {
+        case 0: v = 256.0 * (double)m + a.base; break;                            // HI
+        case 1: v = (double)m; break;                                             // LO
+        case 2: v = 256.0 * (double)m; break;                                     // F1
+        case 3: v = 65536.0 * (double)m; break;                                   // F2
+        default: v = 16777216.0 * (double)(m < 128 ? m : m - 256) + a.off; break;  // F3
+      }
       double sn, cs;
       sincos(g * v, &sn, &cs);
-      a.tab[(size_t)r * kTabEntries + e] = make_double2(cs, -sn);
+      a.tab[(size_t)r * kTabRow + e] = make_double2(cs, -sn);
     }
   }
 }
@@ -223,7 +259,7 @@ __device__ __forceinline__ void block_sum2(double& x, double& y, double* scratch
 struct SweepArgs {
   void* psi;
   const void* diag;
-  const double2* ptab; // phase tables (integer cost vectors), kTabEntries per layer
+  const double2* ptab; // phase tables (integer cost vectors), kTabRow per layer
   double* partials;   // 2 doubles per block (E, norm) when F_EXPV
   double diag_offset;
   double amp0;        // 2^{-n/2} for F_INIT
@@ -249,7 +285,7 @@ struct LayerParams {
 
 __device__ __forceinline__ LayerParams layer_params(const SweepArgs& a, uint32_t set, int l) {
   const size_t r = (size_t)(a.set0 + set) * a.p_total + a.layer0 + l;
-  return LayerParams{a.pset[3 * r], a.pset[3 * r + 1], a.pset[3 * r + 2], a.ptab + r * kTabEntries};
+  return LayerParams{a.pset[3 * r], a.pset[3 * r + 1], a.pset[3 * r + 2], a.ptab + r * kTabRow};
 }
 
 // gate cos(b) I - i sin(b) X on the pair (y0, y1):
@@ -265,14 +301,32 @@ __device__ __forceinline__ void rx_pair(double& r0, double& i0, double& r1, doub
 template <class S, int EB>
 __device__ __forceinline__ void exchange_c(double (&vr)[1 << EB], double (&vi)[1 << EB], typename S::L* lds,
                                            uint32_t tid, int wf, int wt) {
-  // linear swizzle: per-thread part once, per-register part uniform
-  const uint32_t pf = swz<S::kBytes>(thr_part<EB>(tid, wf)), pt = swz<S::kBytes>(thr_part<EB>(tid, wt));
+  if constexpr (S::kSplit) {
+    // real parts, then imaginary parts, as 8-byte entries
+    double* d = reinterpret_cast<double*>(lds);
+    const uint32_t pf = swz<8>(thr_part<EB>(tid, wf)), pt = swz<8>(thr_part<EB>(tid, wt));
 #pragma unroll
-  for (int k = 0; k < (1 << EB); ++k) S::lput(lds, pf ^ swz<S::kBytes>((uint32_t)k << wf), vr[k], vi[k]);
-  __syncthreads();
+    for (int k = 0; k < (1 << EB); ++k) d[pf ^ swz<8>((uint32_t)k << wf)] = vr[k];
+    __syncthreads();
 #pragma unroll
-  for (int k = 0; k < (1 << EB); ++k) S::lget(lds, pt ^ swz<S::kBytes>((uint32_t)k << wt), vr[k], vi[k]);
-  __syncthreads();
+    for (int k = 0; k < (1 << EB); ++k) vr[k] = d[pt ^ swz<8>((uint32_t)k << wt)];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < (1 << EB); ++k) d[pf ^ swz<8>((uint32_t)k << wf)] = vi[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < (1 << EB); ++k) vi[k] = d[pt ^ swz<8>((uint32_t)k << wt)];
+    __syncthreads();
+  } else {
+    // linear swizzle: per-thread part once, per-register part uniform
+    const uint32_t pf = swz<S::kBytes>(thr_part<EB>(tid, wf)), pt = swz<S::kBytes>(thr_part<EB>(tid, wt));
+#pragma unroll
+    for (int k = 0; k < (1 << EB); ++k) S::lput(lds, pf ^ swz<S::kBytes>((uint32_t)k << wf), vr[k], vi[k]);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < (1 << EB); ++k) S::lget(lds, pt ^ swz<S::kBytes>((uint32_t)k << wt), vr[k], vi[k]);
+    __syncthreads();
+  }
 }
 
 // exp(-i g c) evaluated directly from the double-precision angle g * c.  Kept
@@ -291,47 +345,75 @@ __device__ __forceinline__ void cmul_inplace(double& r, double& i, double fr, do
   r = nr; i = ni;
 }
 
+// Table passes of the integer phase.  Every pass multiplies each element by
+// T[(x >> 8) & 255] * T[256 + (x & 255)] with x = (v + add) >> shift, where v is
+// the stored value and T the 512 entries staged in LDS:
+//   in range (one pass):  T = HI|LO, add = -base, shift 0;
+//   out of range (int32): T = F1|LO, then T = F3|F2 with shift 16 (the byte
+//   decomposition).
+// One code path serves both cases, so the rare case costs no registers in the
+// common one.  Returns the number of passes; prepare_pass stages pass `pass`.
+__device__ __forceinline__ void prepare_pass(double2* tab, const double2* row, uint32_t tid, int pass) {
+  __syncthreads();  // readers of the previous tables are done
+  for (uint32_t e = tid; e < 256u; e += blockDim.x) {
+    if (pass == 0) {
+      tab[e] = row[512 + e];  // F1 (LO stays)
+    } else {
+      tab[e] = row[1024 + e];       // F3
+      tab[256 + e] = row[768 + e];  // F2
+    }
+  }
+  __syncthreads();
+}
+
+// Stage HI|LO and decide (workgroup-uniform) whether every value of the tile is
+// covered by it.
+template <class D, int E>
+__device__ __forceinline__ bool stage_phase_tables(const typename D::RawT (&cv)[E], double2* tab, const double2* row,
+                                                   uint32_t tid) {
+  int ok = 1;
+  if constexpr (!D::kAlwaysInTable) {
+#pragma unroll
+    for (int k = 0; k < E; ++k) ok &= (D::tab_index(cv[k]) >= 0);
+  }
+  for (uint32_t e = tid; e < (uint32_t)kTabEntries; e += blockDim.x) tab[e] = row[e];
+  if constexpr (D::kAlwaysInTable) {
+    __syncthreads();
+    return true;
+  } else {
+    return !__syncthreads_or(!ok);
+  }
+}
+
 // Phase operator of one layer on the thread's register elements, from the
 // stored cost values `cv` of those elements.  Integer cost vectors use the
-// LDS-staged tables; if any element of the workgroup falls outside the table
-// range the whole workgroup takes the direct path (a workgroup-uniform branch).
+// LDS-staged tables (one pass, or two byte-table passes when some int32 value
+// of the workgroup is outside the two-level table; a workgroup-uniform choice);
+// float64 ones evaluate sincos of the angle.
 template <class S, class D, int EB>
 __device__ __forceinline__ void phase_from_raw(double (&vr)[1 << EB], double (&vi)[1 << EB],
                                                const typename D::RawT (&cv)[1 << EB], const SweepArgs& a,
                                                const LayerParams& lp, uint32_t tid, double2* tab) {
   constexpr int E = 1 << EB;
   if constexpr (D::kTable) {
-    int ok = 1;
-    if constexpr (!D::kAlwaysInTable) {
-#pragma unroll
-      for (int k = 0; k < E; ++k) ok &= (D::tab_index(cv[k]) >= 0);
-    }
-    for (uint32_t e = tid; e < (uint32_t)kTabEntries; e += blockDim.x) tab[e] = lp.tab[e];
-    bool fast;
-    if constexpr (D::kAlwaysInTable) {
-      __syncthreads();
-      fast = true;
-    } else {
-      fast = !__syncthreads_or(!ok);
-    }
-    if (fast) {
+    const bool fast = stage_phase_tables<D, E>(cv, tab, lp.tab, tid);
+    const int npass = fast ? 1 : 2;
+    const uint32_t add = fast ? (uint32_t)(-(int32_t)D::kTableBase) : 0u;
+#pragma clang loop unroll(disable)
+    for (int pass = 0; pass < npass; ++pass) {
+      if (!fast) prepare_pass(tab, lp.tab, tid, pass);
+      const int shift = pass ? 16 : 0;
       // groups of four elements: bounds how many table entries the scheduler
       // keeps in flight (register pressure decides occupancy here)
 #pragma unroll
       for (int k0 = 0; k0 < E; k0 += 4) {
 #pragma unroll
         for (int k = k0; k < k0 + 4 && k < E; ++k) {
-          const int32_t u = D::tab_index(cv[k]);
-          const double2 h = tab[u >> 8], lo = tab[256 + (u & 255)];
+          const uint32_t x = ((uint32_t)cv[k] + add) >> shift;
+          const double2 h = tab[(x >> 8) & 255u], lo = tab[256 + (x & 255u)];
           cmul_inplace(vr[k], vi[k], fma(h.x, lo.x, -h.y * lo.y), fma(h.x, lo.y, h.y * lo.x));
         }
         __builtin_amdgcn_sched_barrier(0);
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < E; ++k) {
-        const double2 f = phase_direct(lp.g, D::value(cv[k]) + a.diag_offset);
-        cmul_inplace(vr[k], vi[k], f.x, f.y);
       }
     }
   } else {
@@ -415,11 +497,11 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
 //          tile's mixer gates of layer l+1 (valid when this sweep is the last
 //          of layer l: every other gate of layer l is already applied)
 template <class S, class D, int EB, bool INIT, bool PHASE, bool EXPV, bool FUSE>
-__global__ void __launch_bounds__(512, S::kMinWavesPerSimd) qaoa_sweep_kernel(const SweepArgs a) {
+__global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_sweep_kernel(const SweepArgs a) {
   constexpr int E = 1 << EB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   typename S::L* lds = reinterpret_cast<typename S::L*>(smem_raw);
-  double2* tab = reinterpret_cast<double2*>(smem_raw + (1u << a.g.tb) * S::kBytes);
+  double2* tab = reinterpret_cast<double2*>(smem_raw + (1u << a.g.tb) * S::kLdsBytes);
   const uint32_t tid = threadIdx.x;
   const uint64_t base = block_base(xcd_block(blockIdx.x, gridDim.x), a.g);
   const uint32_t set = blockIdx.y;
@@ -498,7 +580,7 @@ __global__ void __launch_bounds__(512) qaoa_tile_kernel(const SweepArgs a) {
   constexpr int E = 1 << EB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   typename S::L* lds = reinterpret_cast<typename S::L*>(smem_raw);
-  double2* tab = reinterpret_cast<double2*>(smem_raw + (1u << a.g.tb) * S::kBytes);
+  double2* tab = reinterpret_cast<double2*>(smem_raw + (1u << a.g.tb) * S::kLdsBytes);
   const uint32_t tid = threadIdx.x;
   const uint32_t set = blockIdx.x;
   void* psi = reinterpret_cast<char*>(a.psi) + (uint64_t)set * a.set_stride_bytes;
@@ -549,7 +631,7 @@ struct AdjArgs {
   void* psi;           // forward state, uncomputed in place
   void* lam;           // adjoint state
   const void* diag;
-  const double2* ptab; // phase tables, kTabEntries per layer row
+  const double2* ptab; // phase tables, kTabRow per layer row
   const double* pset;  // rows (gamma, cos beta, sin beta)
   double* partials;    // this launch's (beta term, gamma term) per block
   double* partials2;   // A_FUSE: the beta term of layer - 1 per block (gamma term 0)
@@ -609,29 +691,26 @@ __device__ __forceinline__ void undo_phase(double (&vr)[1 << EB], double (&vi)[1
   constexpr int E = 1 << EB;
 #pragma unroll
   for (int k = 0; k < E; ++k) gacc += (D::value(cv[k]) + a.diag_offset) * (lr[k] * vi[k] - li[k] * vr[k]);
-  bool fast = false;
   if constexpr (D::kTable) {
-    int ok = 1;
-    if constexpr (!D::kAlwaysInTable) {
+    const bool fast = stage_phase_tables<D, E>(cv, tab, lp.tab, tid);
+    const int npass = fast ? 1 : 2;
+    const uint32_t add = fast ? (uint32_t)(-(int32_t)D::kTableBase) : 0u;
+#pragma clang loop unroll(disable)
+    for (int pass = 0; pass < npass; ++pass) {
+      if (!fast) prepare_pass(tab, lp.tab, tid, pass);
+      const int shift = pass ? 16 : 0;
 #pragma unroll
-      for (int k = 0; k < E; ++k) ok &= (D::tab_index(cv[k]) >= 0);
-    }
-    for (uint32_t e = tid; e < (uint32_t)kTabEntries; e += blockDim.x) tab[e] = lp.tab[e];
-    fast = !__syncthreads_or(!ok);
-  }
-  if (fast) {
-    // groups of four elements bound the table entries in flight (registers)
+      for (int k0 = 0; k0 < E; k0 += 4) {
 #pragma unroll
-    for (int k0 = 0; k0 < E; k0 += 4) {
-#pragma unroll
-      for (int k = k0; k < k0 + 4 && k < E; ++k) {
-        const int32_t u = D::tab_index(cv[k]);
-        const double2 h = tab[u >> 8], lo = tab[256 + (u & 255)];
-        const double fr = fma(h.x, lo.x, -h.y * lo.y), fi = -fma(h.x, lo.y, h.y * lo.x);  // conjugate
-        cmul_inplace(vr[k], vi[k], fr, fi);
-        cmul_inplace(lr[k], li[k], fr, fi);
+        for (int k = k0; k < k0 + 4 && k < E; ++k) {
+          const uint32_t x = ((uint32_t)cv[k] + add) >> shift;
+          const double2 h = tab[(x >> 8) & 255u], lo = tab[256 + (x & 255u)];
+          const double fr = fma(h.x, lo.x, -h.y * lo.y), fi = -fma(h.x, lo.y, h.y * lo.x);  // conjugate
+          cmul_inplace(vr[k], vi[k], fr, fi);
+          cmul_inplace(lr[k], li[k], fr, fi);
+        }
+        __builtin_amdgcn_sched_barrier(0);
       }
-      __builtin_amdgcn_sched_barrier(0);
     }
   } else {
 #pragma unroll
@@ -654,11 +733,11 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_kernel(const AdjArgs a) {
   constexpr int E = 1 << EB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   typename S::L* lds = reinterpret_cast<typename S::L*>(smem_raw);
-  double2* tab = reinterpret_cast<double2*>(smem_raw + (1u << a.g.tb) * S::kBytes);
+  double2* tab = reinterpret_cast<double2*>(smem_raw + (1u << a.g.tb) * S::kLdsBytes);
   const uint32_t tid = threadIdx.x;
   const uint64_t base = block_base(xcd_block(blockIdx.x, gridDim.x), a.g);
   const size_t r = (size_t)a.layer;
-  const LayerParams lp{a.pset[3 * r], a.pset[3 * r + 1], a.pset[3 * r + 2], a.ptab + r * kTabEntries};
+  const LayerParams lp{a.pset[3 * r], a.pset[3 * r + 1], a.pset[3 * r + 2], a.ptab + r * kTabRow};
   const int w_load = a.g.tb - EB;
   int w = w_load;
   double vr[E], vi[E], lr[E], li[E];
@@ -729,8 +808,8 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_tile_kernel(const AdjArgs a)
   constexpr int E = 1 << EB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   typename S::L* lds = reinterpret_cast<typename S::L*>(smem_raw);
-  double2* tab = reinterpret_cast<double2*>(smem_raw + (1u << a.g.tb) * S::kBytes);
-  double* scratch = reinterpret_cast<double*>(smem_raw + (1u << a.g.tb) * S::kBytes + kTabEntries * sizeof(double2));
+  double2* tab = reinterpret_cast<double2*>(smem_raw + (1u << a.g.tb) * S::kLdsBytes);
+  double* scratch = reinterpret_cast<double*>(smem_raw + (1u << a.g.tb) * S::kLdsBytes + D::kTabLds * sizeof(double2));
   const uint32_t tid = threadIdx.x;
   const int w_load = a.g.tb - EB;
   int w = w_load;
@@ -746,7 +825,7 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_tile_kernel(const AdjArgs a)
     li[k] = c * vi[k];
   }
   for (int l = a.nlayers - 1; l >= 0; --l) {
-    const LayerParams lp{a.pset[3 * l], a.pset[3 * l + 1], a.pset[3 * l + 2], a.ptab + (size_t)l * kTabEntries};
+    const LayerParams lp{a.pset[3 * l], a.pset[3 * l + 1], a.pset[3 * l + 2], a.ptab + (size_t)l * kTabRow};
     double xacc = 0.0, gacc = 0.0;
     w = undo_mixer<S, EB>(vr, vi, lr, li, lds, a.g, tid, w, lp.ca, lp.sb, xacc);
     if (w != w_load) {

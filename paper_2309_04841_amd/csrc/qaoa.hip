@@ -57,10 +57,10 @@ int tile_bits_for_bytes(size_t elem_bytes, int cap) {
   while (tb < cap && ((size_t)1 << (tb + 1)) * elem_bytes <= 65536) ++tb;
   return tb;
 }
-// Minimum passenger bits so that a high sweep touches >= 128 contiguous bytes.
-int min_passenger_bits(size_t elem_bytes) {
+// Minimum passenger bits so that a high sweep touches >= run_bytes contiguous bytes.
+int min_passenger_bits(size_t elem_bytes, size_t run_bytes = 128) {
   int p = 0;
-  while (((size_t)1 << p) * elem_bytes < 128) ++p;
+  while (((size_t)1 << p) * elem_bytes < run_bytes) ++p;
   return p;
 }
 
@@ -90,6 +90,7 @@ qk::TileGeom make_geom(int tb, int R, int hA, int qA, int qB, int act_lo, int eb
 // Sweep plan covering all n qubits with tiles of at most tbmax bits.
 struct Plan {
   bool single;          // whole vector in one tile
+  bool wide;            // complex128 tiles of up to 2^14 elements (qk::C128W)
   int eb;               // register bits per thread
   std::vector<qk::TileGeom> sweeps;
 };
@@ -107,10 +108,11 @@ int page_bit(size_t elem_bytes) {
 // qubits.  m0 and the split are chosen to minimise the largest number of
 // page-selecting qubits in any sweep (2^that = pages a workgroup touches),
 // keeping the sweep count of the plain split.
-Plan make_plan(int n, size_t elem_bytes, int eb = kEB) {
+Plan make_plan(int n, size_t elem_bytes, int eb = kEB, int tb_cap = 0, size_t run_bytes = 128) {
   Plan pl;
-  const int tbmax = tile_bits_for_bytes(elem_bytes, 9 + eb);
-  const int pmin = min_passenger_bits(elem_bytes);
+  pl.wide = false;
+  const int tbmax = tb_cap ? tb_cap : tile_bits_for_bytes(elem_bytes, 9 + eb);
+  const int pmin = min_passenger_bits(elem_bytes, run_bytes);
   const int smin = pmin;  // store runs of >= 128 B
   if (n <= tbmax) {
     pl.single = true;
@@ -162,6 +164,24 @@ Plan make_plan(int n, size_t elem_bytes, int eb = kEB) {
 }
 
 uint64_t plan_blocks(int n, const qk::TileGeom& g) { return (uint64_t)1 << (n - g.tb); }
+
+// Forward plan of a state.  complex128 states above 2^14 elements also try
+// 2^14-element tiles (qk::C128W), first with 128-byte passenger runs, then
+// with 64-byte runs, and take them when they need fewer sweeps per layer.
+constexpr int kWideTileBits = 14;
+Plan state_plan(int n, int state_dtype) {
+  const size_t S = state_elem_bytes(state_dtype);
+  Plan best = make_plan(n, S);
+  if (state_dtype != QAOA_C128 || n <= kWideTileBits) return best;
+  for (size_t run : {(size_t)128, (size_t)64}) {
+    Plan w = make_plan(n, S, kEB, kWideTileBits, run);
+    if (w.sweeps.size() < best.sweeps.size()) {
+      w.wide = true;
+      best = w;
+    }
+  }
+  return best;
+}
 
 // Launch order of a multi-tile evaluation.  The mixer gates of a layer commute
 // (one gate per qubit), so layer l runs its sweeps in plan order when l is
@@ -221,8 +241,8 @@ Plan adjoint_plan(int n, size_t state_bytes) { return make_plan(n, state_bytes, 
 // used after the tile and the tables are done with.
 template <class S, class D>
 size_t tile_lds_bytes(const qk::TileGeom& g, uint32_t threads, bool phase) {
-  const size_t tile = ((size_t)1 << g.tb) * S::kBytes;
-  const size_t tab = (D::kTable && phase) ? qk::kTabEntries * sizeof(double2) : 0;
+  const size_t tile = ((size_t)1 << g.tb) * S::kLdsBytes;
+  const size_t tab = (D::kTable && phase) ? D::kTabLds * sizeof(double2) : 0;
   return std::max<size_t>(tile + tab, std::max<size_t>(16, 2 * threads) * sizeof(double));
 }
 
@@ -268,8 +288,9 @@ int launch_sweep_s(const qk::SweepArgs& a, int diag_dtype, uint64_t blocks, uint
 }
 
 // One sweep over `blocks` tiles of each of `sets` states.
-int launch_sweep(const qk::SweepArgs& a, int state_dtype, int diag_dtype, uint64_t blocks, uint32_t sets,
+int launch_sweep(const qk::SweepArgs& a, int state_dtype, int diag_dtype, bool wide, uint64_t blocks, uint32_t sets,
                  hipStream_t st) {
+  if (state_dtype == QAOA_C128 && wide) return launch_sweep_s<qk::C128W>(a, diag_dtype, blocks, sets, st);
   if (state_dtype == QAOA_C128) return launch_sweep_s<qk::C128>(a, diag_dtype, blocks, sets, st);
   return launch_sweep_s<qk::C64>(a, diag_dtype, blocks, sets, st);
 }
@@ -309,8 +330,8 @@ void launch_tile(const qk::SweepArgs& a, int state_dtype, int diag_dtype, int eb
 template <class S, class D, bool FIRST, bool PHASE, bool FUSE>
 void launch_adj_f(const qk::AdjArgs& a, uint64_t blocks, hipStream_t st) {
   const uint32_t threads = 1u << (a.g.tb - kEBAdj);
-  const size_t tile = ((size_t)1 << a.g.tb) * S::kBytes;
-  const size_t lds = std::max<size_t>(tile + qk::kTabEntries * sizeof(double2), std::max<size_t>(16, 2 * threads) * sizeof(double));
+  const size_t tile = ((size_t)1 << a.g.tb) * S::kLdsBytes;
+  const size_t lds = std::max<size_t>(tile + D::kTabLds * sizeof(double2), std::max<size_t>(16, 2 * threads) * sizeof(double));
   hipLaunchKernelGGL((qk::qaoa_adjoint_kernel<S, D, kEBAdj, FIRST, PHASE, FUSE>), dim3((uint32_t)blocks),
                      dim3(threads), lds, st, a);
 }
@@ -330,7 +351,7 @@ int launch_adj_d(const qk::AdjArgs& a, int flags, uint64_t blocks, hipStream_t s
 template <class S, class D, int EB>
 void launch_adj_tile_t(const qk::AdjArgs& a, hipStream_t st) {
   const uint32_t threads = 1u << (a.g.tb - EB);
-  const size_t lds = ((size_t)1 << a.g.tb) * S::kBytes + qk::kTabEntries * sizeof(double2) +
+  const size_t lds = ((size_t)1 << a.g.tb) * S::kLdsBytes + D::kTabLds * sizeof(double2) +
                      std::max<size_t>(16, 2 * threads) * sizeof(double);
   hipLaunchKernelGGL((qk::qaoa_adjoint_tile_kernel<S, D, EB>), dim3(1), dim3(threads), lds, st, a);
 }
@@ -464,7 +485,7 @@ int int_stats(int n, const int32_t* data, int32_t lowmask, void* work, int64_t o
 constexpr size_t kStatWork = (3 * kStatBlocks + 4) * sizeof(int64_t);
 
 // Evolve workspace layout: [per-state (E, norm) partials of the last sweep]
-// [parameter rows: 3 doubles each][phase tables: kTabEntries double2 per row].
+// [parameter rows: 3 doubles each][phase tables: kTabRow double2 per row].
 // A single evaluation with host angles uses kPrepRows rows (one chunk of
 // layers at a time, plus the next layer); a batch with device angles uses
 // batch * p rows.
@@ -476,12 +497,13 @@ struct EvolveWork {
 };
 EvolveWork evolve_work(int n, size_t states, size_t rows, int state_dtype) {
   EvolveWork b{};
-  const Plan pl = make_plan(n, state_elem_bytes(state_dtype));
-  const uint64_t last = plan_blocks(n, pl.sweeps.back());
+  const Plan pl = state_plan(n, state_dtype);
+  uint64_t last = 0;  // most workgroups of any sweep (the last sweep depends on p)
+  for (const auto& g : pl.sweeps) last = std::max(last, plan_blocks(n, g));
   b.partials_stride = 2 * std::max<uint64_t>(last, kExpectBlocks);
   b.partials_bytes = sizeof(double) * b.partials_stride * states;
   b.pset_bytes = ((3 * sizeof(double) * rows + 255) / 256) * 256;
-  b.tab_bytes = rows * qk::kTabEntries * sizeof(double2);
+  b.tab_bytes = rows * qk::kTabRow * sizeof(double2);
   b.tmp_bytes = sizeof(double) * 2 * kReduceChunks * states;
   b.total = b.partials_bytes + b.pset_bytes + b.tab_bytes + b.tmp_bytes;
   return b;
@@ -522,7 +544,7 @@ GradWork grad_work(int n, int p, int state_dtype) {
   g.fwd = evolve_work_bytes(n, state_dtype);
   g.pset_off = g.fwd;
   g.tab_off = g.pset_off + ((3 * sizeof(double) * (size_t)p + 255) / 256) * 256;
-  g.rev_off = g.tab_off + (size_t)p * qk::kTabEntries * sizeof(double2);
+  g.rev_off = g.tab_off + (size_t)p * qk::kTabRow * sizeof(double2);
   g.layer_stride = 2 * pl.sweeps.size() * blocks;
   g.total = g.rev_off + sizeof(double) * g.layer_stride * (size_t)p;
   return g;
@@ -772,6 +794,7 @@ static int enqueue_evolve(int n, int p, int batch, const double* h_gamma, const 
   pa.pset = pset;
   pa.tab = use_tab ? tab : nullptr;
   pa.base = use_tab ? table_base(diag_dtype, diag_offset) : 0.0;
+  pa.off = diag_offset;
   auto prep = [&](int l0, int nl) -> int {  // host angles, layers [l0, l0 + nl), nl <= kPrepRows
     pa.rows = nl;
     for (int i = 0; i < nl; ++i) { pa.gamma[i] = h_gamma[l0 + i]; pa.beta[i] = h_beta[l0 + i]; }
@@ -787,7 +810,7 @@ static int enqueue_evolve(int n, int p, int batch, const double* h_gamma, const 
     LAUNCH_CHECK("layer_prep_kernel");
   }
 
-  const Plan pl = make_plan(n, S);
+  const Plan pl = state_plan(n, state_dtype);
   qk::SweepArgs a{};
   a.diag = d_diag;
   a.diag_offset = diag_offset;
@@ -829,7 +852,7 @@ static int enqueue_evolve(int n, int p, int batch, const double* h_gamma, const 
         a.layer0 = host_angles ? stp.layer - l0 : stp.layer;
         a.flags = stp.flags;
         last_blocks = plan_blocks(n, a.g);
-        rc = launch_sweep(a, state_dtype, diag_dtype, last_blocks, sets, st);
+        rc = launch_sweep(a, state_dtype, diag_dtype, pl.wide, last_blocks, sets, st);
         if (rc) return rc;
         LAUNCH_CHECK("qaoa_sweep_kernel");
       }
@@ -948,7 +971,7 @@ int qaoa_plan_describe(int kind, int n, int state_dtype, int elem_bytes, int* ou
   Plan pl;
   if (kind == 0 || kind == 1) {
     if (!valid_state_dtype(state_dtype)) return -fail(QAOA_ERR_INVALID, "bad state dtype %d", state_dtype);
-    pl = kind == 0 ? make_plan(n, state_elem_bytes(state_dtype)) : adjoint_plan(n, state_elem_bytes(state_dtype));
+    pl = kind == 0 ? state_plan(n, state_dtype) : adjoint_plan(n, state_elem_bytes(state_dtype));
   } else if (kind == 2) {
     if (elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8) return -fail(QAOA_ERR_INVALID, "bad elem_bytes");
     pl = make_plan(n, (size_t)elem_bytes);
@@ -959,6 +982,7 @@ int qaoa_plan_describe(int kind, int n, int state_dtype, int elem_bytes, int* ou
   v.push_back((int)pl.sweeps.size());
   v.push_back(pl.eb);
   v.push_back(pl.single ? 1 : 0);
+  v.push_back(pl.wide ? 1 : 0);
   for (const auto& g : pl.sweeps) {
     v.push_back(g.tb); v.push_back(g.R); v.push_back(g.hA); v.push_back(g.qA); v.push_back(g.qB);
     v.push_back(g.act_lo); v.push_back(g.w_store); v.push_back(g.nchunks);
@@ -974,7 +998,7 @@ int qaoa_schedule_describe(int kind, int n, int p, int state_dtype, int init, in
   if (p < 0) return -fail(QAOA_ERR_INVALID, "p < 0");
   if (!valid_state_dtype(state_dtype)) return -fail(QAOA_ERR_INVALID, "bad state dtype %d", state_dtype);
   const size_t S = state_elem_bytes(state_dtype);
-  const Plan pl = kind == 0 ? make_plan(n, S) : adjoint_plan(n, S);
+  const Plan pl = kind == 0 ? state_plan(n, state_dtype) : adjoint_plan(n, S);
   if (pl.single) return 0;
   const std::vector<SweepStep> sched = kind == 0 ? sweep_schedule((int)pl.sweeps.size(), p, init != 0, reduce != 0)
                                                  : adjoint_schedule((int)pl.sweeps.size(), p);
@@ -1026,8 +1050,9 @@ int qaoa_grad(int n, int p, const double* gamma, const double* beta, const void*
   for (int l0 = 0; l0 < p; l0 += 32) {
     qk::PrepArgs pa{};
     pa.pset = pset + 3 * (size_t)l0;
-    pa.tab = use_tab ? tab + (size_t)l0 * qk::kTabEntries : nullptr;
+    pa.tab = use_tab ? tab + (size_t)l0 * qk::kTabRow : nullptr;
     pa.base = use_tab ? table_base(diag_dtype, diag_offset) : 0.0;
+    pa.off = diag_offset;
     pa.rows = std::min(32, p - l0);
     for (int i = 0; i < pa.rows; ++i) { pa.gamma[i] = gamma[l0 + i]; pa.beta[i] = beta[l0 + i]; }
     hipLaunchKernelGGL(qk::layer_prep_kernel, dim3(pa.rows), dim3(256), 0, st, pa);

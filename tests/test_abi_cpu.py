@@ -41,9 +41,9 @@ def test_version_and_last_error():
 
 def test_workspace_bytes():
     # per-block (E, norm) partials of the last sweep + parameter rows (256-byte aligned) and
-    # phase tables of 33 layers (a chunk of 32 and the next one) + the first stage of the
-    # two-stage reduction
-    assert _lib.workspace_bytes(_lib.QAOA_OP_EVOLVE, 26, _lib.QAOA_C128) == 16 * (1 << 14) + 1024 + 33 * 512 * 16 + 16 * 1024
+    # phase tables (5 x 256 entries) of 33 layers (a chunk of 32 and the next one) + the
+    # first stage of the two-stage reduction
+    assert _lib.workspace_bytes(_lib.QAOA_OP_EVOLVE, 26, _lib.QAOA_C128) == 16 * (1 << 12) + 1024 + 33 * 1280 * 16 + 16 * 1024
     assert _lib.workspace_bytes(_lib.QAOA_OP_PRECOMPUTE, 20, diag_dtype=_lib.QAOA_DIAG_F64) == 0
     assert _lib.workspace_bytes(_lib.QAOA_OP_PRECOMPUTE, 20, diag_dtype=_lib.QAOA_DIAG_U16) >= 4 << 20
     with pytest.raises(_lib.QaoaError):
@@ -205,18 +205,23 @@ def bank_conflict_degree(elem_bytes, tb, w, eb=4):
 
 def _check_plan(n, plan, elem_bytes, emulate):
     eb = plan["eb"]
+    wide = plan.get("wide", False)
+    # wide complex128 tiles pass through LDS as 8-byte halves, 1024 threads
+    lds_elem, max_thread_bits, lds_cap = (8, 10, 131072) if wide else (elem_bytes, 9, 65536)
+    if wide:
+        assert elem_bytes == 16 and n > 14
     seen = []
     for si, s in enumerate(plan["sweeps"]):
         tb, R, hA, qA, qB, act_lo = s["tb"], s["R"], s["hA"], s["qA"], s["qB"], s["act_lo"]
         hB = tb - R - hA
         assert 1 <= tb <= n and 0 <= R <= tb and 0 <= hA and hB >= 0
-        assert tb - eb <= 9, "more than 512 threads"
-        assert (1 << tb) * elem_bytes <= 65536, "tile exceeds 64 KiB of LDS"
+        assert tb - eb <= max_thread_bits, "too many threads"
+        assert (1 << tb) * lds_elem <= lds_cap, "tile exceeds its LDS buffer"
         assert R <= qA and qA + hA <= qB and qB + hB <= n, "segments must be ordered and inside n"
         if si == 0:
             assert act_lo == 0
         else:
-            assert act_lo == R and (1 << R) * elem_bytes >= 128, "high sweeps move >= 128 contiguous bytes"
+            assert act_lo == R and (1 << R) * elem_bytes >= (64 if wide else 128), "contiguous bytes per run"
         gbits = [global_bit(s, t) for t in range(tb)]
         assert len(set(gbits)) == tb and max(gbits) < n
         assert 0 <= s["w_store"] <= tb - eb
@@ -235,7 +240,7 @@ def _check_plan(n, plan, elem_bytes, emulate):
             for w in windows:
                 t = tmap(tid, k, w, eb).ravel()
                 assert np.array_equal(np.sort(t), np.arange(1 << tb))
-                pos = swz(t, elem_bytes)
+                pos = swz(t, lds_elem)
                 assert np.array_equal(np.sort(pos), np.arange(1 << tb))
                 off = tile_off(t, s)
                 blocks = np.arange(1 << (n - tb))[:, None]
@@ -256,11 +261,12 @@ def _page_bits_per_sweep(plan, elem_bytes):
 
 
 def test_page_bits_are_spread():
-    # LABS n=26 complex128 and n=31 complex64: no sweep's tile spans more than
-    # 2^5 pages of 2 MiB (the plain split had 2^7 and 2^9)
+    # LABS n=26 complex128 (two sweeps) and n=31 complex64 (three sweeps): no
+    # sweep's tile spans more than 2^5 pages of 2 MiB (a plain split, one
+    # contiguous high segment per sweep, spans up to 2^9)
     p26 = _lib.plan_describe(26, _lib.QAOA_C128)
     p31 = _lib.plan_describe(31, _lib.QAOA_C64)
-    assert max(_page_bits_per_sweep(p26, 16)) <= 4
+    assert max(_page_bits_per_sweep(p26, 16)) <= 5
     assert max(_page_bits_per_sweep(p31, 8)) <= 5
 
 
@@ -268,7 +274,7 @@ def test_page_bits_are_spread():
 def test_state_plans(sdt, eb):
     for n in range(1, _lib.QAOA_MAX_QUBITS + 1):
         plan = _lib.plan_describe(n, sdt)
-        _check_plan(n, plan, eb, emulate=n <= 17)
+        _check_plan(n, plan, eb, emulate=n <= 17 or (plan["wide"] and n <= 22))
         if plan["single"]:
             assert len(plan["sweeps"]) == 1
 
@@ -288,10 +294,20 @@ def test_adjoint_plans(sdt, eb):
 
 
 def test_headline_plans_sweep_counts():
-    # LABS n=26 complex128 and n=31 complex64 both take three HBM sweeps per layer
-    assert len(_lib.plan_describe(26, _lib.QAOA_C128)["sweeps"]) == 3
+    # LABS n=26 complex128: two sweeps per layer with 2^14-element tiles and
+    # 64-byte runs; n=31 complex64: three sweeps
+    p26 = _lib.plan_describe(26, _lib.QAOA_C128)
+    assert p26["wide"] and len(p26["sweeps"]) == 2
+    assert len(_lib.schedule_describe(26, 10, _lib.QAOA_C128)) == 11
     assert len(_lib.plan_describe(31, _lib.QAOA_C64)["sweeps"]) == 3
     assert _lib.plan_describe(12, _lib.QAOA_C128)["single"]
+    # wide tiles only where they save a sweep
+    for n in range(1, _lib.QAOA_MAX_QUBITS + 1):
+        pl = _lib.plan_describe(n, _lib.QAOA_C128)
+        if pl["wide"]:
+            assert n > 14 and len(pl["sweeps"]) < len(_lib.plan_describe(n, _lib.QAOA_C64)["sweeps"]) + 1
+    assert [n for n in range(15, 35) if _lib.plan_describe(n, _lib.QAOA_C128)["wide"]] == [22, 23, 24, 25, 26] + \
+        list(range(31, 35))
 
 
 @pytest.mark.parametrize("sdt,elem", [(_lib.QAOA_C128, 16), (_lib.QAOA_C64, 8)])
@@ -300,14 +316,15 @@ def test_lds_swizzle_conflict_free(sdt, elem):
     used = set()
     for n in range(1, _lib.QAOA_MAX_QUBITS + 1):
         plan = _lib.plan_describe(n, sdt)
+        lds_elem = 8 if plan["wide"] else elem
         for sw in plan["sweeps"]:
             if sw["tb"] - plan["eb"] < 6:
                 continue  # fewer than 64 threads: single partial wave
             for w in {c[0] for c in sw["chunks"]} | {sw["w_store"], sw["tb"] - plan["eb"]}:
-                used.add((sw["tb"], w))
+                used.add((lds_elem, sw["tb"], w))
     assert used
-    for tb, w in sorted(used):
-        assert bank_conflict_degree(elem, tb, w) == 1, (tb, w)
+    for lds_elem, tb, w in sorted(used):
+        assert bank_conflict_degree(lds_elem, tb, w) == 1, (lds_elem, tb, w)
 
 
 def test_server_validation():
@@ -366,10 +383,13 @@ def test_schedule_is_a_reordering_of_the_layers(n, sdt, p, init, reduce):
 
 
 def test_schedule_counts_and_fusion():
-    # LABS n=26 complex128, p=10: 3 sweeps per layer fused to 21 launches
-    sched = _lib.schedule_describe(26, 10, _lib.QAOA_C128)
+    # LABS n=31 complex64, p=10: 3 sweeps per layer fused to 21 launches;
+    # n=26 complex128: 2 sweeps per layer, 11 launches
+    sched = _lib.schedule_describe(31, 10, _lib.QAOA_C64)
     assert len(sched) == 21
     assert sum(1 for s in sched if s[2] & _lib.F_FUSE) == 9
+    sched = _lib.schedule_describe(26, 10, _lib.QAOA_C128)
+    assert len(sched) == 11 and sum(1 for s in sched if s[2] & _lib.F_FUSE) == 9
     with pytest.raises(_lib.QaoaError):
         _lib.schedule_describe(0, 1)
     with pytest.raises(_lib.QaoaError):

@@ -164,6 +164,40 @@ def test_evolve_labs_ramp(q, n, dtype, ddt):
     _compare(n, psi, eo, oracle.diag_labs(n).astype(np.float64), gamma, beta, dtype)
 
 
+@pytest.mark.parametrize("n,p", [(22, 3), (23, 2), (25, 1)])
+def test_evolve_wide_complex128_tiles(q, n, p):
+    # 2^22..2^25 complex128 elements run 2^14-element tiles (1024 threads, LDS
+    # exchanges split into real and imaginary passes), two sweeps per layer
+    from paper_2309_04841_amd import _lib
+    assert _lib.plan_describe(n, _lib.QAOA_C128)["wide"]
+    gamma, beta = W.linear_ramp(p, seed=n)
+    if n % 2:
+        terms = W.maxcut_terms(W.random_regular_graph(3, n, seed=n))
+    else:
+        terms = W.labs_terms(n)
+    _say(f"evolve wide n={n} p={p}")
+    diag, off = _c_of(q, n, terms, "i32")
+    psi, eo = _run(q, n, diag, off, gamma, beta, "complex128")
+    _compare(n, psi, eo, oracle.diag_terms(n, terms), gamma, beta, "complex128")
+
+
+@pytest.mark.parametrize("n,dtype", [(10, "complex128"), (16, "complex128"), (22, "complex128"),
+                                     (12, "complex64"), (18, "complex64")])
+def test_evolve_int32_beyond_two_level_table(q, n, dtype):
+    # most int32 cost values lie outside [-2^15, 2^15): those workgroups take the
+    # two-pass byte-table phase (single tile, narrow, wide and complex64 tiles)
+    p = 3
+    terms = W.random_terms(n, 4 * n, seed=50 + n, max_order=3, integer=True, wmax=9000)
+    c = oracle.diag_terms(n, terms)
+    assert np.abs(c).max() >= 32768
+    rng = np.random.default_rng(77 + n)
+    gamma, beta = rng.uniform(-0.05, 0.05, size=p), rng.uniform(-np.pi, np.pi, size=p)
+    _say(f"evolve int32 wide range n={n} {dtype}")
+    diag, off = _c_of(q, n, terms, "i32")
+    psi, eo = _run(q, n, diag, off, gamma, beta, dtype)
+    _compare(n, psi, eo, c, gamma, beta, dtype)
+
+
 @pytest.mark.parametrize("dtype", ["complex128", "complex64"])
 def test_evolve_weighted_maxcut_f64_diag(q, dtype):
     n = 16
