@@ -172,7 +172,7 @@ def test_evolve_wide_complex128_tiles(q, n, p):
     assert _lib.plan_describe(n, _lib.QAOA_C128)["wide"]
     gamma, beta = W.linear_ramp(p, seed=n)
     if n % 2:
-        terms = W.maxcut_terms(W.random_regular_graph(3, n, seed=n))
+        terms = W.maxcut_terms(W.random_regular_graph(4, n, seed=n))  # d n must be even
     else:
         terms = W.labs_terms(n)
     _say(f"evolve wide n={n} p={p}")
