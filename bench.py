@@ -138,7 +138,7 @@ def bench_batch(args):
 
 def bench_serve(args):
     """Served mix: Poisson arrivals at --rate, 60% objective / 40% gradient,
-    LABS or 3-regular MaxCut with n ~ U{16..30}, p ~ U{1..20}, complex64;
+    LABS or 3-regular (odd n: 4-regular) MaxCut with n ~ U{16..30}, p ~ U{1..20}, complex64;
     p50/p99 latency and requests/s, vs the same requests run one at a time."""
     import threading
 
@@ -153,7 +153,8 @@ def bench_serve(args):
     probs = {}
     for n in ns:
         probs[("labs", n)] = (n, W.labs_terms(n))
-        probs[("maxcut", n)] = (n, W.maxcut_terms(W.random_regular_graph(3, n, seed=100 + n)))
+        d = 3 if n % 2 == 0 else 4  # d n must be even
+        probs[("maxcut", n)] = (n, W.maxcut_terms(W.random_regular_graph(d, n, seed=100 + n)))
     pids = {k: srv.add_problem(n, terms) for k, (n, terms) in probs.items()}
     keys = list(probs)
     reqs = []
@@ -207,6 +208,10 @@ def main(argv=None):
     ap.add_argument("--sets-per-pass", type=int, default=0, help="batch: states advanced together (0 = autotune)")
     ap.add_argument("--requests", type=int, default=120, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=40.0, help="serve: Poisson arrival rate (requests/s)")
+    ap.add_argument("--wide-tiles", type=int, choices=(0, 1), default=1,
+                    help="complex128: 2^14-element tiles when they save a sweep (library tuning knob)")
+    ap.add_argument("--fuse-layers", type=int, choices=(0, 1), default=1,
+                    help="join adjacent layers in one sweep launch (library tuning knob)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -242,6 +247,8 @@ def main(argv=None):
     from paper_2309_04841_amd import _lib
     import workloads as W
 
+    _lib.set_tuning(_lib.TUNE_WIDE_TILES, args.wide_tiles)
+    _lib.set_tuning(_lib.TUNE_FUSE_LAYERS, args.fuse_layers)
     spec = CONFIGS[args.config]
     cfg = getattr(W, spec["make"])()
     n, p = cfg["n"], cfg["p"]
@@ -318,6 +325,8 @@ def main(argv=None):
             "workload": cfg["name"], "problem": "LABS", "n": n, "p": p, "state": cfg["dtype"],
             "cost_vector": {"i32": "int32", "u16": "uint16", "f64": "float64"}[spec["diag"]],
             "schedule": "linear ramp, seeded", "sweeps_per_layer": len(plan["sweeps"]),
+            "tile_bits": plan["sweeps"][0]["tb"], "wide_tiles": args.wide_tiles, "fuse_layers": args.fuse_layers,
+            "launches_per_eval": len(sched),
             "precompute_ms": precompute_ms, "E": float(e_last[0]), "norm": float(e_last[1]),
             "wall_s_timed": wall,
         },

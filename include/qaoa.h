@@ -74,6 +74,21 @@ const char *qaoa_version(void);
 /* Message describing the last failing call made by this host thread ("" if none). */
 const char *qaoa_last_error(void);
 
+/* Process-wide tuning knobs.  They select sweep plans and the launch order
+ * only: results change at most in rounding order.  Workspace sizes follow the
+ * current setting, so set knobs before sizing workspaces; a call made with a
+ * workspace sized under another setting fails with QAOA_ERR_NOMEM rather than
+ * overrun it.
+ *   QAOA_TUNE_WIDE_TILES  1 (default): complex128 states use 2^14-element tiles
+ *                         when that saves a sweep per layer; 0: never.
+ *   QAOA_TUNE_FUSE_LAYERS 1 (default): the sweep ending a layer also starts the
+ *                         next one (evaluation and gradient); 0: one launch per
+ *                         sweep and layer.
+ * qaoa_set_tuning returns QAOA_ERR_INVALID for an unknown knob or value. */
+enum { QAOA_TUNE_WIDE_TILES = 0, QAOA_TUNE_FUSE_LAYERS = 1 };
+int qaoa_set_tuning(int knob, int value);
+int qaoa_get_tuning(int knob, int *value);
+
 /* Workspace size in bytes that `op` needs for n qubits with the given dtypes
  * (for QAOA_OP_PRECOMPUTE: the worst case over all term sets).  Writes *bytes.
  * Returns QAOA_ERR_INVALID for bad arguments. */

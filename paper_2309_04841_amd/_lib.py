@@ -24,7 +24,8 @@ EXPORTS = ("qaoa_version", "qaoa_last_error", "qaoa_workspace_bytes", "qaoa_prec
            "qaoa_evolve", "qaoa_expectation", "qaoa_grad", "qaoa_plan_describe", "qaoa_evolve_batch",
            "qaoa_batch_workspace_bytes", "qaoa_grad_workspace_bytes", "qaoa_server_create",
            "qaoa_server_destroy", "qaoa_server_add_problem", "qaoa_server_submit", "qaoa_server_wait",
-           "qaoa_server_stats_get", "qaoa_server_reset_stats", "qaoa_schedule_describe")
+           "qaoa_server_stats_get", "qaoa_server_reset_stats", "qaoa_schedule_describe", "qaoa_set_tuning",
+           "qaoa_get_tuning")
 
 _STATUS_NAMES = {0: "QAOA_OK", 1: "QAOA_ERR_INVALID", 2: "QAOA_ERR_RANGE", 3: "QAOA_ERR_NOMEM",
                  4: "QAOA_ERR_DEVICE", 5: "QAOA_ERR_UNSUPPORTED"}
@@ -58,6 +59,10 @@ def _load() -> ctypes.CDLL:
     lib.qaoa_grad.argtypes = [I, I, P, P, P, I, D, SZ, P, P, I, SZ, P, P, SZ, P]
     lib.qaoa_plan_describe.restype = I
     lib.qaoa_plan_describe.argtypes = [I, I, I, I, P, I]
+    lib.qaoa_set_tuning.restype = I
+    lib.qaoa_set_tuning.argtypes = [I, I]
+    lib.qaoa_get_tuning.restype = I
+    lib.qaoa_get_tuning.argtypes = [I, ctypes.POINTER(I)]
     lib.qaoa_schedule_describe.restype = I
     lib.qaoa_schedule_describe.argtypes = [I, I, I, I, I, I, P, I]
     lib.qaoa_grad_workspace_bytes.restype = I
@@ -154,6 +159,39 @@ def plan_describe(n: int, state_dtype: int = QAOA_C128, elem_bytes: int = 0, kin
 
 
 F_INIT, F_PHASE, F_EXPV, F_FUSE = 1, 2, 4, 8
+
+
+TUNE_WIDE_TILES, TUNE_FUSE_LAYERS = 0, 1
+
+
+def set_tuning(knob: int, value: int) -> None:
+    check(lib.qaoa_set_tuning(knob, int(value)))
+
+
+def get_tuning(knob: int) -> int:
+    v = ctypes.c_int(0)
+    check(lib.qaoa_get_tuning(knob, ctypes.byref(v)))
+    return int(v.value)
+
+
+class tuning:
+    """Context manager: `with tuning(wide_tiles=0, fuse_layers=0): ...` restores the previous values."""
+
+    def __init__(self, wide_tiles: int | None = None, fuse_layers: int | None = None):
+        self._want = {TUNE_WIDE_TILES: wide_tiles, TUNE_FUSE_LAYERS: fuse_layers}
+        self._saved = {}
+
+    def __enter__(self):
+        for k, v in self._want.items():
+            if v is not None:
+                self._saved[k] = get_tuning(k)
+                set_tuning(k, v)
+        return self
+
+    def __exit__(self, *exc):
+        for k, v in self._saved.items():
+            set_tuning(k, v)
+        return False
 
 
 A_FIRST, A_PHASE, A_FUSE = 1, 2, 8

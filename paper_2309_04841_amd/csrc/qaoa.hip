@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -169,10 +170,12 @@ uint64_t plan_blocks(int n, const qk::TileGeom& g) { return (uint64_t)1 << (n - 
 // 2^14-element tiles (qk::C128W), first with 128-byte passenger runs, then
 // with 64-byte runs, and take them when they need fewer sweeps per layer.
 constexpr int kWideTileBits = 14;
+std::atomic<int> g_wide_tiles{1};   // QAOA_TUNE_WIDE_TILES
+std::atomic<int> g_fuse_layers{1};  // QAOA_TUNE_FUSE_LAYERS
 Plan state_plan(int n, int state_dtype) {
   const size_t S = state_elem_bytes(state_dtype);
   Plan best = make_plan(n, S);
-  if (state_dtype != QAOA_C128 || n <= kWideTileBits) return best;
+  if (state_dtype != QAOA_C128 || n <= kWideTileBits || !g_wide_tiles.load()) return best;
   for (size_t run : {(size_t)128, (size_t)64}) {
     Plan w = make_plan(n, S, kEB, kWideTileBits, run);
     if (w.sweeps.size() < best.sweeps.size()) {
@@ -201,6 +204,12 @@ struct SweepStep {
 // qubits.  `layer` is the layer undone first; flags are qk::A_*.
 std::vector<SweepStep> adjoint_schedule(int nsw, int p) {
   std::vector<SweepStep> out;
+  if (!g_fuse_layers.load()) {  // layers p-1..0, sweeps nsw-1..0, phase undone in sweep 0
+    for (int l = p - 1; l >= 0; --l)
+      for (int sw = nsw - 1; sw >= 0; --sw)
+        out.push_back(SweepStep{sw, l, (l == p - 1 && sw == nsw - 1 ? qk::A_FIRST : 0) | (sw == 0 ? qk::A_PHASE : 0)});
+    return out;
+  }
   for (int l = p - 1; l >= 0; --l) {
     const int r = p - 1 - l;
     for (int i = (l == p - 1 ? 0 : 1); i < nsw; ++i) {  // position 0 of layer l < p-1 ran fused
@@ -216,6 +225,15 @@ std::vector<SweepStep> adjoint_schedule(int nsw, int p) {
 
 std::vector<SweepStep> sweep_schedule(int nsw, int p, bool init, bool expv) {
   std::vector<SweepStep> out;
+  if (!g_fuse_layers.load()) {  // every layer in plan order, phase in its first sweep
+    for (int l = 0; l < p; ++l)
+      for (int sw = 0; sw < nsw; ++sw) {
+        int flags = sw == 0 ? qk::F_PHASE | ((l == 0 && init) ? qk::F_INIT : 0) : 0;
+        if (l == p - 1 && sw == nsw - 1 && expv) flags |= qk::F_EXPV;
+        out.push_back(SweepStep{sw, l, flags});
+      }
+    return out;
+  }
   for (int l = 0; l < p; ++l) {
     for (int i = (l == 0 ? 0 : 1); i < nsw; ++i) {  // position 0 of layer l > 0 ran fused
       const int sw = (l & 1) ? nsw - 1 - i : i;
@@ -564,7 +582,25 @@ __attribute__((visibility("hidden"))) int qaoa_internal_set_error(int code, cons
 
 extern "C" {
 
-const char* qaoa_version(void) { return "0.2.0"; }
+const char* qaoa_version(void) { return "0.3.0"; }
+
+int qaoa_set_tuning(int knob, int value) {
+  if (value != 0 && value != 1) return fail(QAOA_ERR_INVALID, "tuning value must be 0 or 1, got %d", value);
+  switch (knob) {
+    case QAOA_TUNE_WIDE_TILES: g_wide_tiles.store(value); return QAOA_OK;
+    case QAOA_TUNE_FUSE_LAYERS: g_fuse_layers.store(value); return QAOA_OK;
+    default: return fail(QAOA_ERR_INVALID, "unknown tuning knob %d", knob);
+  }
+}
+
+int qaoa_get_tuning(int knob, int* value) {
+  if (!value) return fail(QAOA_ERR_INVALID, "value is NULL");
+  switch (knob) {
+    case QAOA_TUNE_WIDE_TILES: *value = g_wide_tiles.load(); return QAOA_OK;
+    case QAOA_TUNE_FUSE_LAYERS: *value = g_fuse_layers.load(); return QAOA_OK;
+    default: return fail(QAOA_ERR_INVALID, "unknown tuning knob %d", knob);
+  }
+}
 
 const char* qaoa_last_error(void) { return g_err.c_str(); }
 

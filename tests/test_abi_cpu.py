@@ -347,7 +347,13 @@ def _sweep_qubits(s):
                                    (31, _lib.QAOA_C64), (34, _lib.QAOA_C64), (14, _lib.QAOA_C64)])
 @pytest.mark.parametrize("p", [1, 2, 3, 10, 33, 64])
 @pytest.mark.parametrize("init,reduce", [(True, True), (False, False)])
-def test_schedule_is_a_reordering_of_the_layers(n, sdt, p, init, reduce):
+@pytest.mark.parametrize("fuse,wide", [(1, 1), (0, 1), (1, 0)])
+def test_schedule_is_a_reordering_of_the_layers(n, sdt, p, init, reduce, fuse, wide):
+    with _lib.tuning(wide_tiles=wide, fuse_layers=fuse):
+        _check_schedule(n, sdt, p, init, reduce, fuse)
+
+
+def _check_schedule(n, sdt, p, init, reduce, fuse):
     """Flattened, the launches must apply phase(l) then one gate per qubit of
     layer l, for l = 0..p-1 in order; gates of one layer may come in any order
     (they commute), nothing else may move (Sections 3.1-3.2)."""
@@ -357,7 +363,7 @@ def test_schedule_is_a_reordering_of_the_layers(n, sdt, p, init, reduce):
         assert sched == []
         return
     nsw = len(plan["sweeps"])
-    assert len(sched) == 1 + (nsw - 1) * p
+    assert len(sched) == (1 + (nsw - 1) * p if fuse else nsw * p)
     ops = []
     for i, (sw, layer, flags) in enumerate(sched):
         qs = _sweep_qubits(plan["sweeps"][sw])
@@ -399,7 +405,13 @@ def test_schedule_counts_and_fusion():
 @pytest.mark.parametrize("n,sdt", [(12, _lib.QAOA_C128), (18, _lib.QAOA_C128), (26, _lib.QAOA_C128),
                                    (31, _lib.QAOA_C64), (16, _lib.QAOA_C64)])
 @pytest.mark.parametrize("p", [1, 2, 3, 10, 40])
-def test_adjoint_schedule_undoes_layers_in_reverse(n, sdt, p):
+@pytest.mark.parametrize("fuse", [1, 0])
+def test_adjoint_schedule_undoes_layers_in_reverse(n, sdt, p, fuse):
+    with _lib.tuning(fuse_layers=fuse):
+        _check_adjoint_schedule(n, sdt, p, fuse)
+
+
+def _check_adjoint_schedule(n, sdt, p, fuse):
     """Flattened, the reverse pass must undo, for l = p-1 .. 0, one gate per
     qubit of layer l (any order) and then layer l's phase; lambda = c psi is
     formed by the first launch only; every (layer, sweep) partial slot is
@@ -411,7 +423,7 @@ def test_adjoint_schedule_undoes_layers_in_reverse(n, sdt, p):
         assert sched == []
         return
     nsw = len(plan["sweeps"])
-    assert len(sched) == 1 + (nsw - 1) * p
+    assert len(sched) == (1 + (nsw - 1) * p if fuse else nsw * p)
     ops, slots = [], []
     for i, (sw, layer, flags) in enumerate(sched):
         qs = _sweep_qubits(plan["sweeps"][sw])
@@ -433,3 +445,18 @@ def test_adjoint_schedule_undoes_layers_in_reverse(n, sdt, p):
         assert ops[pos] == ("unphase", layer)
         pos += 1
     assert pos == len(ops)
+
+
+def test_tuning_knobs():
+    assert _lib.get_tuning(_lib.TUNE_WIDE_TILES) == 1 and _lib.get_tuning(_lib.TUNE_FUSE_LAYERS) == 1
+    with _lib.tuning(wide_tiles=0):
+        assert not _lib.plan_describe(26, _lib.QAOA_C128)["wide"]
+        assert len(_lib.plan_describe(26, _lib.QAOA_C128)["sweeps"]) == 3
+    assert _lib.plan_describe(26, _lib.QAOA_C128)["wide"]
+    with _lib.tuning(fuse_layers=0):
+        assert len(_lib.schedule_describe(26, 10, _lib.QAOA_C128)) == 20
+    for bad in ((2, 1), (0, 2), (-1, 0)):
+        with pytest.raises(_lib.QaoaError):
+            _lib.set_tuning(*bad)
+    with pytest.raises(_lib.QaoaError):
+        _lib.get_tuning(7)
