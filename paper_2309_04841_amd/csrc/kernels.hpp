@@ -165,10 +165,11 @@ struct DF64 {
 // A layer's row holds HI, LO, F1, F2, F3 (256 double2 (cos, -sin) each).
 constexpr int kTabEntries = 512;  // HI then LO: the part staged for in-range values
 constexpr int kTabRow = 1280;     // row stride: HI, LO, F1, F2, F3
+constexpr int kParamRow = 4;      // doubles per parameter row: gamma, cos beta, sin beta, tan beta
 
 // Per-layer parameters, computed on the device for every path so that batched
 // and single evaluations use bit-identical values: row r gets
-// pset[3r..3r+2] = (gamma, cos beta, sin beta) and, when tab != nullptr, the
+// pset[4r..4r+3] = (gamma, cos beta, sin beta, tan beta) and, when tab != nullptr, the
 // phase tables tab[512 r ..].  Angles come from device arrays (gamma_d, beta_d)
 // or, when those are null, from the kernel arguments (at most kPrepRows rows).
 struct PrepArgs {
@@ -191,9 +192,10 @@ __global__ void __launch_bounds__(256) layer_prep_kernel(const PrepArgs a) {
     const double b = a.beta_d ? a.beta_d[r] : a.beta[r];
     double sb, cb;
     sincos(b, &sb, &cb);
-    a.pset[3 * r] = g;
-    a.pset[3 * r + 1] = cb;
-    a.pset[3 * r + 2] = sb;
+    a.pset[kParamRow * r] = g;
+    a.pset[kParamRow * r + 1] = cb;
+    a.pset[kParamRow * r + 2] = sb;
+    a.pset[kParamRow * r + 3] = sb / cb;
   }
   if (a.tab != nullptr) {
     for (int e = threadIdx.x; e < kTabRow; e += blockDim.x) {
@@ -279,13 +281,14 @@ struct SweepArgs {
 };
 
 struct LayerParams {
-  double g, ca, sb;
+  double g, ca, sb, tn;  // gamma, cos beta, sin beta, tan beta
   const double2* tab;
 };
 
 __device__ __forceinline__ LayerParams layer_params(const SweepArgs& a, uint32_t set, int l) {
   const size_t r = (size_t)(a.set0 + set) * a.p_total + a.layer0 + l;
-  return LayerParams{a.pset[3 * r], a.pset[3 * r + 1], a.pset[3 * r + 2], a.ptab + r * kTabRow};
+  const double* row = a.pset + kParamRow * r;
+  return LayerParams{row[0], row[1], row[2], row[3], a.ptab + r * kTabRow};
 }
 
 // gate cos(b) I - i sin(b) X on the pair (y0, y1):
@@ -296,6 +299,33 @@ __device__ __forceinline__ void rx_pair(double& r0, double& i0, double& r1, doub
   const double nr1 = fma(a, r1, s * i0);
   const double ni1 = fma(a, i1, -s * r0);
   r0 = nr0; i0 = ni0; r1 = nr1; i1 = ni1;
+}
+
+// The same gate divided by cos(b): (y0, y1) -> (y0 - i t y1, y1 - i t y0) with
+// t = tan(b), four FMAs per pair instead of eight operations.  A sweep applies
+// it to each of its k qubits and multiplies the tile by cos(b)^k afterwards.
+// Every element carries the same factor, so relative precision is unchanged;
+// in double the growth 1/|cos b|^k stays finite for every representable b and
+// k <= 14 (|cos b| >= ~1e-19), and tiles are rescaled before the next layer.
+__device__ __forceinline__ void rx_pair_t(double& r0, double& i0, double& r1, double& i1, double t) {
+  const double nr0 = fma(t, i1, r0);
+  const double ni0 = fma(-t, r1, i0);
+  const double nr1 = fma(t, i0, r1);
+  const double ni1 = fma(-t, r0, i1);
+  r0 = nr0; i0 = ni0; r1 = nr1; i1 = ni1;
+}
+
+// x^k for small k by repeated multiplication.
+__device__ __forceinline__ double ipow(double x, int k) {
+  double r = 1.0;
+  for (int i = 0; i < k; ++i) r *= x;
+  return r;
+}
+
+template <int E>
+__device__ __forceinline__ void scale_tile(double (&vr)[E], double (&vi)[E], double f) {
+#pragma unroll
+  for (int k = 0; k < E; ++k) { vr[k] *= f; vi[k] *= f; }
 }
 
 template <class S, int EB>
@@ -441,10 +471,12 @@ __device__ __forceinline__ void load_cost(typename D::RawT (&cv)[1 << EB], const
 
 // Mixer gates of one layer on the tile's active qubits, window by window, in
 // chunk order or (REV) in reverse chunk order; the gates commute, so both
-// orders give the same layer.  Returns the final window.
+// orders give the same layer.  Each gate is applied divided by cos(beta)
+// (rx_pair_t with tn = tan beta): the caller multiplies the tile by
+// cos(beta)^(tb - act_lo).  Returns the final window.
 template <class S, int EB, bool REV = false>
 __device__ __forceinline__ int apply_mixer(double (&vr)[1 << EB], double (&vi)[1 << EB], typename S::L* lds,
-                                           const TileGeom& g, uint32_t tid, int w, double ca, double sb) {
+                                           const TileGeom& g, uint32_t tid, int w, double tn) {
   constexpr int E = 1 << EB;
   for (int i = 0; i < g.nchunks; ++i) {
     const Chunk ch = g.chunk[REV ? g.nchunks - 1 - i : i];
@@ -457,7 +489,7 @@ __device__ __forceinline__ int apply_mixer(double (&vr)[1 << EB], double (&vi)[1
       if (j >= ch.jlo && j < ch.jhi) {
 #pragma unroll
         for (int k = 0; k < E; ++k) {
-          if (!(k & (1 << j))) rx_pair(vr[k], vi[k], vr[k | (1 << j)], vi[k | (1 << j)], ca, sb);
+          if (!(k & (1 << j))) rx_pair_t(vr[k], vi[k], vr[k | (1 << j)], vi[k | (1 << j)], tn);
         }
       }
     }
@@ -536,12 +568,15 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
     load_cost<D, EB>(pc, a, base, tid, w);
     phase_from_raw<S, D, EB>(vr, vi, pc, a, lp, tid, tab);
   }
-  w = apply_mixer<S, EB>(vr, vi, lds, a.g, tid, w, lp.ca, lp.sb);
+  const int nq = a.g.tb - a.g.act_lo;  // gates per layer in this tile
+  w = apply_mixer<S, EB>(vr, vi, lds, a.g, tid, w, lp.tn);
+  scale_tile(vr, vi, ipow(lp.ca, nq));
   if constexpr (FUSE) {
     const LayerParams lq = layer_params(a, set, 1);
     if constexpr (!kEarlyCost) load_cost<D, EB>(cv, a, base, tid, w);
     phase_from_raw<S, D, EB>(vr, vi, cv, a, lq, tid, tab);
-    w = apply_mixer<S, EB, true>(vr, vi, lds, a.g, tid, w, lq.ca, lq.sb);  // ends in the load mapping
+    w = apply_mixer<S, EB, true>(vr, vi, lds, a.g, tid, w, lq.tn);  // ends in the load mapping
+    scale_tile(vr, vi, ipow(lq.ca, nq));
   }
 
   double e_part = 0.0, n_part = 0.0;
@@ -601,8 +636,9 @@ __global__ void __launch_bounds__(512) qaoa_tile_kernel(const SweepArgs a) {
     load_cost<D, EB>(pc, a, 0, tid, w);
     phase_from_raw<S, D, EB>(vr, vi, pc, a, lp, tid, tab);
     // alternate the chunk order: each layer starts in the window the last one ended in
-    if (l & 1) w = apply_mixer<S, EB, true>(vr, vi, lds, a.g, tid, w, lp.ca, lp.sb);
-    else w = apply_mixer<S, EB>(vr, vi, lds, a.g, tid, w, lp.ca, lp.sb);
+    if (l & 1) w = apply_mixer<S, EB, true>(vr, vi, lds, a.g, tid, w, lp.tn);
+    else w = apply_mixer<S, EB>(vr, vi, lds, a.g, tid, w, lp.tn);
+    scale_tile(vr, vi, ipow(lp.ca, a.g.tb));
   }
   double e_part = 0.0, n_part = 0.0;
   if (a.flags & F_EXPV) expv_partials<D, EB>(vr, vi, a, 0, tid, w, e_part, n_part);
@@ -737,7 +773,8 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_kernel(const AdjArgs a) {
   const uint32_t tid = threadIdx.x;
   const uint64_t base = block_base(xcd_block(blockIdx.x, gridDim.x), a.g);
   const size_t r = (size_t)a.layer;
-  const LayerParams lp{a.pset[3 * r], a.pset[3 * r + 1], a.pset[3 * r + 2], a.ptab + r * kTabRow};
+  const double* prow = a.pset + kParamRow * r;
+  const LayerParams lp{prow[0], prow[1], prow[2], prow[3], a.ptab + r * kTabRow};
   const int w_load = a.g.tb - EB;
   int w = w_load;
   double vr[E], vi[E], lr[E], li[E];
@@ -767,7 +804,8 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_kernel(const AdjArgs a) {
   if constexpr (FUSE) {
     undo_phase<D, EB>(vr, vi, lr, li, cv, a, lp, tab, tid, gacc);
     const size_t r1 = r - 1;
-    w = undo_mixer<S, EB, true>(vr, vi, lr, li, lds, a.g, tid, w, a.pset[3 * r1 + 1], a.pset[3 * r1 + 2], xacc2);
+    w = undo_mixer<S, EB, true>(vr, vi, lr, li, lds, a.g, tid, w, a.pset[kParamRow * r1 + 1],
+                                      a.pset[kParamRow * r1 + 2], xacc2);
   }
   const int w_out = PHASE ? w_load : (FUSE ? w : a.g.w_store);
   if (w != w_out) {
@@ -825,7 +863,8 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_tile_kernel(const AdjArgs a)
     li[k] = c * vi[k];
   }
   for (int l = a.nlayers - 1; l >= 0; --l) {
-    const LayerParams lp{a.pset[3 * l], a.pset[3 * l + 1], a.pset[3 * l + 2], a.ptab + (size_t)l * kTabRow};
+    const double* prow = a.pset + kParamRow * (size_t)l;
+    const LayerParams lp{prow[0], prow[1], prow[2], prow[3], a.ptab + (size_t)l * kTabRow};
     double xacc = 0.0, gacc = 0.0;
     w = undo_mixer<S, EB>(vr, vi, lr, li, lds, a.g, tid, w, lp.ca, lp.sb, xacc);
     if (w != w_load) {

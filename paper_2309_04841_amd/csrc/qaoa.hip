@@ -520,7 +520,7 @@ EvolveWork evolve_work(int n, size_t states, size_t rows, int state_dtype) {
   for (const auto& g : pl.sweeps) last = std::max(last, plan_blocks(n, g));
   b.partials_stride = 2 * std::max<uint64_t>(last, kExpectBlocks);
   b.partials_bytes = sizeof(double) * b.partials_stride * states;
-  b.pset_bytes = ((3 * sizeof(double) * rows + 255) / 256) * 256;
+  b.pset_bytes = ((qk::kParamRow * sizeof(double) * rows + 255) / 256) * 256;
   b.tab_bytes = rows * qk::kTabRow * sizeof(double2);
   b.tmp_bytes = sizeof(double) * 2 * kReduceChunks * states;
   b.total = b.partials_bytes + b.pset_bytes + b.tab_bytes + b.tmp_bytes;
@@ -561,7 +561,7 @@ GradWork grad_work(int n, int p, int state_dtype) {
   const uint64_t blocks = pl.single ? 1 : plan_blocks(n, pl.sweeps[0]);
   g.fwd = evolve_work_bytes(n, state_dtype);
   g.pset_off = g.fwd;
-  g.tab_off = g.pset_off + ((3 * sizeof(double) * (size_t)p + 255) / 256) * 256;
+  g.tab_off = g.pset_off + ((qk::kParamRow * sizeof(double) * (size_t)p + 255) / 256) * 256;
   g.rev_off = g.tab_off + (size_t)p * qk::kTabRow * sizeof(double2);
   g.layer_stride = 2 * pl.sweeps.size() * blocks;
   g.total = g.rev_off + sizeof(double) * g.layer_stride * (size_t)p;
@@ -1085,7 +1085,7 @@ int qaoa_grad(int n, int p, const double* gamma, const double* beta, const void*
   const bool use_tab = diag_dtype != QAOA_DIAG_F64;
   for (int l0 = 0; l0 < p; l0 += 32) {
     qk::PrepArgs pa{};
-    pa.pset = pset + 3 * (size_t)l0;
+    pa.pset = pset + qk::kParamRow * (size_t)l0;
     pa.tab = use_tab ? tab + (size_t)l0 * qk::kTabRow : nullptr;
     pa.base = use_tab ? table_base(diag_dtype, diag_offset) : 0.0;
     pa.off = diag_offset;
