@@ -41,11 +41,14 @@ typedef float fvec2 __attribute__((ext_vector_type(2)));
 struct C128 {  // complex128: (double re, double im)
   using L = double2;
   static constexpr int kBytes = 16;
-  static constexpr int kLdsBytes = 16;   // LDS bytes per tile element
-  static constexpr bool kSplit = false;  // exchanges move whole elements
+  // Window changes move the real parts, then the imaginary parts, as 8-byte
+  // entries: a 2^12-element tile needs 32 KiB of LDS (+ 8 KiB of tables), so
+  // four 256-thread workgroups fit a CU, and 8-byte LDS accesses keep the
+  // kernels within 128 VGPRs (16-byte ones spilled there).
+  static constexpr int kLdsBytes = 8;   // LDS bytes per tile element
+  static constexpr bool kSplit = true;  // exchanges move real and imaginary parts separately
   static constexpr int kMaxThreads = 512;
-  // 64 KiB tiles + tables: two workgroups per CU by LDS, two waves per SIMD
-  static constexpr int kMinWavesPerSimd = 2;
+  static constexpr int kMinWavesPerSimd = 4;
   __device__ static __forceinline__ void load(const void* p, uint64_t x, double& r, double& i) {
     const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(p) + x);
     r = v.x; i = v.y;
@@ -87,14 +90,10 @@ struct C64 {  // complex64 storage, FP64 arithmetic in registers
 };
 
 // complex128 in tiles of up to 2^14 elements (256 KiB, more than the LDS):
-// 1024 threads of 16 elements; a window change moves the real parts, then the
-// imaginary parts, through one 128 KiB buffer of doubles.  Used when the larger
-// tile saves a sweep per layer.
+// 1024 threads of 16 elements; window changes go through one 128 KiB buffer of
+// doubles.  Used when the larger tile saves a sweep per layer.
 struct C128W : C128 {
-  static constexpr int kLdsBytes = 8;
-  static constexpr bool kSplit = true;
-  static constexpr int kMaxThreads = 1024;
-  static constexpr int kMinWavesPerSimd = 4;  // one 16-wave workgroup per CU
+  static constexpr int kMaxThreads = 1024;  // one 16-wave workgroup per CU
 };
 
 // Cost-vector policies.  `get` returns the stored value as a double (the
@@ -559,9 +558,10 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
     }
   }
   if constexpr (EXPV) load_cost<D, EB>(cv, a, base, tid, w_load);
-  // complex64 tiles run at four waves per SIMD: their cost values are read
-  // when needed (holding them through the first gates would spill registers)
-  constexpr bool kEarlyCost = S::kMinWavesPerSimd <= 2;
+  // complex64 tiles hold the cost values from the start (their loads overlap
+  // the state loads); complex128 ones read them when needed (holding them
+  // through the first gates would spill registers)
+  constexpr bool kEarlyCost = !S::kSplit;
   if constexpr (FUSE && kEarlyCost) load_cost<D, EB>(cv, a, base, tid, a.g.chunk[a.g.nchunks - 1].w);
   if constexpr (PHASE) {
     typename D::RawT pc[E];

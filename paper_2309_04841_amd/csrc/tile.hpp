@@ -89,7 +89,9 @@ __device__ __forceinline__ uint64_t block_base(uint64_t b, const TileGeom& g) {
 // into the low S bits (so pos is a permutation of the tile).  The maps are
 // chosen so that every register window's access pattern is free of bank
 // conflicts (64 banks x 4 B): for 16-byte elements each group of 16 lanes, for
-// 8-byte elements each group of 32 lanes, hits distinct banks.  Linearity also
+// 8-byte elements each group of 32 lanes, hits distinct banks.  The 8-byte map
+// (split complex128 exchanges and complex64) holds for 16 and 8 elements per
+// thread on tiles of 2^9 .. 2^14 (found by search over GF(2) matrices).  Linearity also
 // splits pos(thr | k << w) = pos(thr) ^ pos(k << w) into a per-thread part and
 // a workgroup-uniform part.
 template <int ELEM_BYTES>
@@ -105,7 +107,7 @@ struct Swz<8> {
   static constexpr int kShift = 5;
   static constexpr int kCols = 9;
   __host__ __device__ static constexpr uint32_t col(int j) {
-    constexpr uint32_t c[9] = {2, 28, 8, 25, 28, 1, 17, 5, 16};
+    constexpr uint32_t c[9] = {26, 14, 19, 24, 6, 23, 3, 20, 8};
     return c[j];
   }
 };
