@@ -41,14 +41,13 @@ typedef float fvec2 __attribute__((ext_vector_type(2)));
 struct C128 {  // complex128: (double re, double im)
   using L = double2;
   static constexpr int kBytes = 16;
-  // Window changes move the real parts, then the imaginary parts, as 8-byte
-  // entries: a 2^12-element tile needs 32 KiB of LDS (+ 8 KiB of tables), so
-  // four 256-thread workgroups fit a CU, and 8-byte LDS accesses keep the
-  // kernels within 128 VGPRs (16-byte ones spilled there).
-  static constexpr int kLdsBytes = 8;   // LDS bytes per tile element
-  static constexpr bool kSplit = true;  // exchanges move real and imaginary parts separately
+  static constexpr int kLdsBytes = 16;   // LDS bytes per tile element
+  static constexpr bool kSplit = false;  // exchanges move whole elements
   static constexpr int kMaxThreads = 512;
-  static constexpr int kMinWavesPerSimd = 4;
+  // 64 KiB tiles + tables: two workgroups per CU by LDS, up to 256 VGPRs.
+  // (Measured: four waves per SIMD at 128 VGPRs, with split exchanges to fit
+  // four workgroups, was slower: the fused kernels spill there.)
+  static constexpr int kMinWavesPerSimd = 2;
   __device__ static __forceinline__ void load(const void* p, uint64_t x, double& r, double& i) {
     const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(p) + x);
     r = v.x; i = v.y;
@@ -90,10 +89,14 @@ struct C64 {  // complex64 storage, FP64 arithmetic in registers
 };
 
 // complex128 in tiles of up to 2^14 elements (256 KiB, more than the LDS):
-// 1024 threads of 16 elements; window changes go through one 128 KiB buffer of
-// doubles.  Used when the larger tile saves a sweep per layer.
+// 1024 threads of 16 elements; a window change moves the real parts, then the
+// imaginary parts, through one 128 KiB buffer of doubles.  Used when the larger
+// tile saves a sweep per layer.
 struct C128W : C128 {
-  static constexpr int kMaxThreads = 1024;  // one 16-wave workgroup per CU
+  static constexpr int kLdsBytes = 8;
+  static constexpr bool kSplit = true;
+  static constexpr int kMaxThreads = 1024;
+  static constexpr int kMinWavesPerSimd = 4;  // one 16-wave workgroup per CU
 };
 
 // Cost-vector policies.  `get` returns the stored value as a double (the

@@ -89,9 +89,10 @@ __device__ __forceinline__ uint64_t block_base(uint64_t b, const TileGeom& g) {
 // into the low S bits (so pos is a permutation of the tile).  The maps are
 // chosen so that every register window's access pattern is free of bank
 // conflicts (64 banks x 4 B): for 16-byte elements each group of 16 lanes, for
-// 8-byte elements each group of 32 lanes, hits distinct banks.  The 8-byte map
-// (split complex128 exchanges and complex64) holds for 16 and 8 elements per
-// thread on tiles of 2^9 .. 2^14 (found by search over GF(2) matrices).  Linearity also
+// 8-byte elements each group of 32 lanes, hits distinct banks, for 16 and 8
+// elements per thread (the 16-byte map on tiles of 2^9 .. 2^12, the 8-byte map,
+// used by complex64 and the split complex128 exchanges, on 2^9 .. 2^14).  The
+// columns were found by a search over GF(2) matrices against that bank model.  Linearity also
 // splits pos(thr | k << w) = pos(thr) ^ pos(k << w) into a per-thread part and
 // a workgroup-uniform part.
 template <int ELEM_BYTES>
@@ -99,8 +100,11 @@ struct Swz;
 template <>
 struct Swz<16> {
   static constexpr int kShift = 4;
-  static constexpr int kCols = 4;
-  __host__ __device__ static constexpr uint32_t col(int j) { return 1u << j; }
+  static constexpr int kCols = 8;
+  __host__ __device__ static constexpr uint32_t col(int j) {
+    constexpr uint32_t c[8] = {15, 13, 9, 14, 6, 3, 1, 9};
+    return c[j];
+  }
 };
 template <>
 struct Swz<8> {

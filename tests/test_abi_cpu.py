@@ -174,7 +174,7 @@ def global_bit(s, t):
 
 
 # LDS swizzle pos = t ^ L(t >> S), L given by its columns (GF(2)-linear)
-SWZ = {16: (4, [1, 2, 4, 8]), 8: (5, [26, 14, 19, 24, 6, 23, 3, 20, 8]),
+SWZ = {16: (4, [15, 13, 9, 14, 6, 3, 1, 9]), 8: (5, [26, 14, 19, 24, 6, 23, 3, 20, 8]),
        4: (5, [1, 2, 4, 8, 16]), 2: (5, [1, 2, 4, 8, 16])}
 
 
@@ -207,7 +207,7 @@ def _check_plan(n, plan, elem_bytes, emulate):
     eb = plan["eb"]
     wide = plan.get("wide", False)
     # wide complex128 tiles pass through LDS as 8-byte halves, 1024 threads
-    lds_elem, max_thread_bits, lds_cap = (8, 10, 131072) if wide else (min(elem_bytes, 8), 9, 65536)
+    lds_elem, max_thread_bits, lds_cap = (8, 10, 131072) if wide else (elem_bytes, 9, 65536)
     if wide:
         assert elem_bytes == 16 and n > 14
     seen = []
@@ -313,21 +313,22 @@ def test_headline_plans_sweep_counts():
 @pytest.mark.parametrize("sdt", [_lib.QAOA_C128, _lib.QAOA_C64])
 @pytest.mark.parametrize("kind", [_lib.PLAN_EVOLVE, _lib.PLAN_ADJOINT])
 def test_lds_swizzle_conflict_free(sdt, kind):
-    # every register window that any state plan uses is free of LDS bank
-    # conflicts; both state dtypes exchange 8-byte entries (complex128 moves
-    # real and imaginary parts in separate passes)
+    # every register window that any plan uses is free of LDS bank conflicts:
+    # complex64 exchanges 8-byte entries, complex128 16-byte ones, or 8-byte
+    # real and imaginary passes in wide tiles
     used = set()
     for n in range(1, _lib.QAOA_MAX_QUBITS + 1):
         plan = _lib.plan_describe(n, sdt, kind=kind)
         eb = plan["eb"]
+        lds_elem = 8 if (sdt == _lib.QAOA_C64 or plan["wide"]) else 16
         for sw in plan["sweeps"]:
             if sw["tb"] - eb < 6:
                 continue  # fewer than 64 threads: single partial wave
             for w in {c[0] for c in sw["chunks"]} | {sw["w_store"], sw["tb"] - eb}:
-                used.add((sw["tb"], w, eb))
+                used.add((lds_elem, sw["tb"], w, eb))
     assert used
-    for tb, w, eb in sorted(used):
-        assert bank_conflict_degree(8, tb, w, eb=eb) == 1, (tb, w, eb)
+    for lds_elem, tb, w, eb in sorted(used):
+        assert bank_conflict_degree(lds_elem, tb, w, eb=eb) == 1, (lds_elem, tb, w, eb)
 
 
 def test_server_validation():
