@@ -486,13 +486,15 @@ __device__ __forceinline__ int apply_mixer(double (&vr)[1 << EB], double (&vi)[1
       exchange_c<S, EB>(vr, vi, lds, tid, w, ch.w);
       w = ch.w;
     }
+    // every register bit takes a butterfly; bits outside [jlo, jhi) take the
+    // identity (t = 0 gives exactly (y0, y1)).  Straight-line code: a branch
+    // per bit made the compiler copy all 16 elements after each butterfly.
 #pragma unroll
     for (int j = 0; j < EB; ++j) {
-      if (j >= ch.jlo && j < ch.jhi) {
+      const double tj = (j >= ch.jlo && j < ch.jhi) ? tn : 0.0;
 #pragma unroll
-        for (int k = 0; k < E; ++k) {
-          if (!(k & (1 << j))) rx_pair_t(vr[k], vi[k], vr[k | (1 << j)], vi[k | (1 << j)], tn);
-        }
+      for (int k = 0; k < E; ++k) {
+        if (!(k & (1 << j))) rx_pair_t(vr[k], vi[k], vr[k | (1 << j)], vi[k | (1 << j)], tj);
       }
     }
   }
@@ -702,17 +704,19 @@ __device__ __forceinline__ int undo_mixer(double (&vr)[1 << EB], double (&vi)[1 
       exchange_c<S, EB>(lr, li, lds, tid, w, ch.w);
       w = ch.w;
     }
+    // straight-line: bits outside [jlo, jhi) take the identity gate (1, 0)
+    // and add nothing to the X term
 #pragma unroll
     for (int j = 0; j < EB; ++j) {
-      if (j >= ch.jlo && j < ch.jhi) {
+      const bool on = (j >= ch.jlo && j < ch.jhi);
+      const double aj = on ? ca : 1.0, sj = on ? -sb : 0.0, mj = on ? 1.0 : 0.0;
 #pragma unroll
-        for (int k = 0; k < E; ++k) {
-          if (!(k & (1 << j))) {
-            const int k1 = k | (1 << j);
-            xacc += xterm(vr[k], vi[k], vr[k1], vi[k1], lr[k], li[k], lr[k1], li[k1]);
-            rx_pair(vr[k], vi[k], vr[k1], vi[k1], ca, -sb);
-            rx_pair(lr[k], li[k], lr[k1], li[k1], ca, -sb);
-          }
+      for (int k = 0; k < E; ++k) {
+        if (!(k & (1 << j))) {
+          const int k1 = k | (1 << j);
+          xacc = fma(mj, xterm(vr[k], vi[k], vr[k1], vi[k1], lr[k], li[k], lr[k1], li[k1]), xacc);
+          rx_pair(vr[k], vi[k], vr[k1], vi[k1], aj, sj);
+          rx_pair(lr[k], li[k], lr[k1], li[k1], aj, sj);
         }
       }
     }
