@@ -332,31 +332,30 @@ __device__ __forceinline__ void scale_tile(double (&vr)[E], double (&vi)[E], dou
 
 template <class S, int EB>
 __device__ __forceinline__ void exchange_c(double (&vr)[1 << EB], double (&vi)[1 << EB], typename S::L* lds,
-                                           uint32_t tid, int wf, int wt) {
+                                           const TileGeom& g, uint32_t tid, int wf, int wt) {
+  // linear swizzle: per-thread part here, per-register part from g.loff
+  const uint32_t pf = swz<S::kLdsBytes>(thr_part<EB>(tid, wf)), pt = swz<S::kLdsBytes>(thr_part<EB>(tid, wt));
   if constexpr (S::kSplit) {
     // real parts, then imaginary parts, as 8-byte entries
     double* d = reinterpret_cast<double*>(lds);
-    const uint32_t pf = swz<8>(thr_part<EB>(tid, wf)), pt = swz<8>(thr_part<EB>(tid, wt));
 #pragma unroll
-    for (int k = 0; k < (1 << EB); ++k) d[pf ^ swz<8>((uint32_t)k << wf)] = vr[k];
+    for (int k = 0; k < (1 << EB); ++k) d[pf ^ g.loff[wf][k]] = vr[k];
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < (1 << EB); ++k) vr[k] = d[pt ^ swz<8>((uint32_t)k << wt)];
+    for (int k = 0; k < (1 << EB); ++k) vr[k] = d[pt ^ g.loff[wt][k]];
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < (1 << EB); ++k) d[pf ^ swz<8>((uint32_t)k << wf)] = vi[k];
+    for (int k = 0; k < (1 << EB); ++k) d[pf ^ g.loff[wf][k]] = vi[k];
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < (1 << EB); ++k) vi[k] = d[pt ^ swz<8>((uint32_t)k << wt)];
+    for (int k = 0; k < (1 << EB); ++k) vi[k] = d[pt ^ g.loff[wt][k]];
     __syncthreads();
   } else {
-    // linear swizzle: per-thread part once, per-register part uniform
-    const uint32_t pf = swz<S::kBytes>(thr_part<EB>(tid, wf)), pt = swz<S::kBytes>(thr_part<EB>(tid, wt));
 #pragma unroll
-    for (int k = 0; k < (1 << EB); ++k) S::lput(lds, pf ^ swz<S::kBytes>((uint32_t)k << wf), vr[k], vi[k]);
+    for (int k = 0; k < (1 << EB); ++k) S::lput(lds, pf ^ g.loff[wf][k], vr[k], vi[k]);
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < (1 << EB); ++k) S::lget(lds, pt ^ swz<S::kBytes>((uint32_t)k << wt), vr[k], vi[k]);
+    for (int k = 0; k < (1 << EB); ++k) S::lget(lds, pt ^ g.loff[wt][k], vr[k], vi[k]);
     __syncthreads();
   }
 }
@@ -463,7 +462,7 @@ __device__ __forceinline__ void load_cost_g(typename D::RawT (&cv)[1 << EB], con
                                             uint32_t tid, int w, const TileGeom& g) {
   const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), g);
 #pragma unroll
-  for (int k = 0; k < (1 << EB); ++k) cv[k] = D::load_raw(diag, xb + tile_off((uint32_t)k << w, g));
+  for (int k = 0; k < (1 << EB); ++k) cv[k] = D::load_raw(diag, xb + g.goff[w][k]);
 }
 template <class D, int EB>
 __device__ __forceinline__ void load_cost(typename D::RawT (&cv)[1 << EB], const SweepArgs& a, uint64_t base,
@@ -483,7 +482,7 @@ __device__ __forceinline__ int apply_mixer(double (&vr)[1 << EB], double (&vi)[1
   for (int i = 0; i < g.nchunks; ++i) {
     const Chunk ch = g.chunk[REV ? g.nchunks - 1 - i : i];
     if (ch.w != w) {
-      exchange_c<S, EB>(vr, vi, lds, tid, w, ch.w);
+      exchange_c<S, EB>(vr, vi, lds, g, tid, w, ch.w);
       w = ch.w;
     }
     // every register bit takes a butterfly; bits outside [jlo, jhi) take the
@@ -509,7 +508,7 @@ __device__ __forceinline__ void expv_partials(const double (&vr)[1 << EB], const
   const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g);
 #pragma unroll
   for (int k = 0; k < (1 << EB); ++k) {
-    const double c = D::get(a.diag, xb + tile_off((uint32_t)k << w, a.g)) + a.diag_offset;
+    const double c = D::get(a.diag, xb + a.g.goff[w][k]) + a.diag_offset;
     const double pr = vr[k] * vr[k] + vi[k] * vi[k];
     e_part += pr * c;
     n_part += pr;
@@ -559,7 +558,7 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
       for (int k = 0; k < E; ++k) { vr[k] = a.amp0; vi[k] = 0.0; }
     } else {
 #pragma unroll
-      for (int k = 0; k < E; ++k) S::load(psi, xb + tile_off((uint32_t)k << w, a.g), vr[k], vi[k]);
+      for (int k = 0; k < E; ++k) S::load(psi, xb + a.g.goff[w][k], vr[k], vi[k]);
     }
   }
   if constexpr (EXPV) load_cost<D, EB>(cv, a, base, tid, w_load);
@@ -587,7 +586,7 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
   double e_part = 0.0, n_part = 0.0;
   const int w_out = EXPV ? w_load : (FUSE ? w : a.g.w_store);
   if (w != w_out) {
-    exchange_c<S, EB>(vr, vi, lds, tid, w, w_out);
+    exchange_c<S, EB>(vr, vi, lds, a.g, tid, w, w_out);
     w = w_out;
   }
   if constexpr (EXPV) {
@@ -601,7 +600,7 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
   {
     const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g);
 #pragma unroll
-    for (int k = 0; k < E; ++k) S::store(psi, xb + tile_off((uint32_t)k << w, a.g), vr[k], vi[k]);
+    for (int k = 0; k < E; ++k) S::store(psi, xb + a.g.goff[w][k], vr[k], vi[k]);
   }
   if constexpr (EXPV) {
     block_sum2(e_part, n_part, reinterpret_cast<double*>(smem_raw));
@@ -648,7 +647,7 @@ __global__ void __launch_bounds__(512) qaoa_tile_kernel(const SweepArgs a) {
   double e_part = 0.0, n_part = 0.0;
   if (a.flags & F_EXPV) expv_partials<D, EB>(vr, vi, a, 0, tid, w, e_part, n_part);
   if (w != a.g.w_store) {
-    exchange_c<S, EB>(vr, vi, lds, tid, w, a.g.w_store);
+    exchange_c<S, EB>(vr, vi, lds, a.g, tid, w, a.g.w_store);
     w = a.g.w_store;
   }
 #pragma unroll
@@ -700,8 +699,8 @@ __device__ __forceinline__ int undo_mixer(double (&vr)[1 << EB], double (&vi)[1 
   for (int i = 0; i < g.nchunks; ++i) {
     const Chunk ch = g.chunk[REV ? g.nchunks - 1 - i : i];
     if (ch.w != w) {
-      exchange_c<S, EB>(vr, vi, lds, tid, w, ch.w);
-      exchange_c<S, EB>(lr, li, lds, tid, w, ch.w);
+      exchange_c<S, EB>(vr, vi, lds, g, tid, w, ch.w);
+      exchange_c<S, EB>(lr, li, lds, g, tid, w, ch.w);
       w = ch.w;
     }
     // straight-line: bits outside [jlo, jhi) take the identity gate (1, 0)
@@ -789,7 +788,7 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_kernel(const AdjArgs a) {
   {
     const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g);
 #pragma unroll
-    for (int k = 0; k < E; ++k) S::load(a.psi, xb + tile_off((uint32_t)k << w, a.g), vr[k], vi[k]);
+    for (int k = 0; k < E; ++k) S::load(a.psi, xb + a.g.goff[w][k], vr[k], vi[k]);
     if constexpr (FIRST || PHASE) load_cost_g<D, EB>(cv, a.diag, base, tid, w, a.g);
     if constexpr (FIRST) {
 #pragma unroll
@@ -800,7 +799,7 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_kernel(const AdjArgs a) {
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < E; ++k) S::load(a.lam, xb + tile_off((uint32_t)k << w, a.g), lr[k], li[k]);
+      for (int k = 0; k < E; ++k) S::load(a.lam, xb + a.g.goff[w][k], lr[k], li[k]);
     }
     // FUSE: cost values in the mapping of the last chunk's window, where the
     // phase is undone
@@ -816,8 +815,8 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_kernel(const AdjArgs a) {
   }
   const int w_out = PHASE ? w_load : (FUSE ? w : a.g.w_store);
   if (w != w_out) {
-    exchange_c<S, EB>(vr, vi, lds, tid, w, w_out);
-    exchange_c<S, EB>(lr, li, lds, tid, w, w_out);
+    exchange_c<S, EB>(vr, vi, lds, a.g, tid, w, w_out);
+    exchange_c<S, EB>(lr, li, lds, a.g, tid, w, w_out);
     w = w_out;
   }
   if constexpr (PHASE) undo_phase<D, EB>(vr, vi, lr, li, cv, a, lp, tab, tid, gacc);
@@ -825,7 +824,7 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_kernel(const AdjArgs a) {
     const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g);
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-      const uint64_t x = xb + tile_off((uint32_t)k << w, a.g);
+      const uint64_t x = xb + a.g.goff[w][k];
       S::store(a.psi, x, vr[k], vi[k]);
       S::store(a.lam, x, lr[k], li[k]);
     }
@@ -875,8 +874,8 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_tile_kernel(const AdjArgs a)
     double xacc = 0.0, gacc = 0.0;
     w = undo_mixer<S, EB>(vr, vi, lr, li, lds, a.g, tid, w, lp.ca, lp.sb, xacc);
     if (w != w_load) {
-      exchange_c<S, EB>(vr, vi, lds, tid, w, w_load);
-      exchange_c<S, EB>(lr, li, lds, tid, w, w_load);
+      exchange_c<S, EB>(vr, vi, lds, a.g, tid, w, w_load);
+      exchange_c<S, EB>(lr, li, lds, a.g, tid, w, w_load);
       w = w_load;
     }
     __syncthreads();  // previous layer's table reads are done

@@ -264,12 +264,21 @@ size_t tile_lds_bytes(const qk::TileGeom& g, uint32_t threads, bool phase) {
   return std::max<size_t>(tile + tab, std::max<size_t>(16, 2 * threads) * sizeof(double));
 }
 
+// A copy of the launch arguments with the per-register offset tables of the
+// geometry filled for state policy S and `eb` register bits.
+template <class S, class Args>
+Args with_offsets(const Args& a, int eb) {
+  Args b = a;
+  qk::fill_reg_offsets<S::kLdsBytes>(b.g, eb);
+  return b;
+}
+
 template <class S, class D, bool INIT, bool PHASE, bool EXPV, bool FUSE = false>
 void launch_sweep_f(const qk::SweepArgs& a, uint64_t blocks, uint32_t sets, hipStream_t st) {
   const uint32_t threads = 1u << (a.g.tb - kEB);
   const size_t lds = tile_lds_bytes<S, D>(a.g, threads, PHASE || FUSE);
   hipLaunchKernelGGL((qk::qaoa_sweep_kernel<S, D, kEB, INIT, PHASE, EXPV, FUSE>), dim3((uint32_t)blocks, sets),
-                     dim3(threads), lds, st, a);
+                     dim3(threads), lds, st, with_offsets<S>(a, kEB));
 }
 
 // One sweep launch.  The schedules only produce these flag combinations: the
@@ -317,7 +326,7 @@ template <class S, class D, int EB>
 void launch_tile_t(const qk::SweepArgs& a, uint32_t sets, hipStream_t st) {
   const uint32_t threads = 1u << (a.g.tb - EB);
   const size_t lds = tile_lds_bytes<S, D>(a.g, threads, true);
-  hipLaunchKernelGGL((qk::qaoa_tile_kernel<S, D, EB>), dim3(sets), dim3(threads), lds, st, a);
+  hipLaunchKernelGGL((qk::qaoa_tile_kernel<S, D, EB>), dim3(sets), dim3(threads), lds, st, with_offsets<S>(a, EB));
 }
 
 template <class S, class D>
@@ -351,7 +360,7 @@ void launch_adj_f(const qk::AdjArgs& a, uint64_t blocks, hipStream_t st) {
   const size_t tile = ((size_t)1 << a.g.tb) * S::kLdsBytes;
   const size_t lds = std::max<size_t>(tile + D::kTabLds * sizeof(double2), std::max<size_t>(16, 2 * threads) * sizeof(double));
   hipLaunchKernelGGL((qk::qaoa_adjoint_kernel<S, D, kEBAdj, FIRST, PHASE, FUSE>), dim3((uint32_t)blocks),
-                     dim3(threads), lds, st, a);
+                     dim3(threads), lds, st, with_offsets<S>(a, kEBAdj));
 }
 
 template <class S, class D>
@@ -371,7 +380,7 @@ void launch_adj_tile_t(const qk::AdjArgs& a, hipStream_t st) {
   const uint32_t threads = 1u << (a.g.tb - EB);
   const size_t lds = ((size_t)1 << a.g.tb) * S::kLdsBytes + D::kTabLds * sizeof(double2) +
                      std::max<size_t>(16, 2 * threads) * sizeof(double);
-  hipLaunchKernelGGL((qk::qaoa_adjoint_tile_kernel<S, D, EB>), dim3(1), dim3(threads), lds, st, a);
+  hipLaunchKernelGGL((qk::qaoa_adjoint_tile_kernel<S, D, EB>), dim3(1), dim3(threads), lds, st, with_offsets<S>(a, EB));
 }
 
 template <class S, class D>

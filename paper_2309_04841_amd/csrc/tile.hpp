@@ -32,6 +32,7 @@
 namespace qk {
 
 constexpr int kMaxChunks = 8;
+constexpr int kMaxWin = 11;  // register windows w in [0, 10] (tiles of up to 2^14, >= 8 elements per thread)
 
 struct Chunk {
   int8_t w;    // register window: tile bits [w, w+EB)
@@ -49,6 +50,13 @@ struct TileGeom {
   int nchunks;  // chunks per layer
   int w_store;  // window the tile is stored from
   Chunk chunk[kMaxChunks];
+  // Per-register parts of the addresses for register window w, filled on the
+  // host (uniform across the workgroup, so the kernels read them with scalar
+  // loads instead of recomputing them at every window change):
+  //   goff[w][k] = tile_off(k << w): global offset of register k
+  //   loff[w][k] = swz(k << w): LDS position part of register k
+  uint64_t goff[kMaxWin][16];
+  uint32_t loff[kMaxWin][16];
 };
 
 template <int EB>
@@ -67,7 +75,7 @@ __device__ __forceinline__ uint32_t thr_part(uint32_t tid, int w) {
 // tile bits to disjoint global bits, so tile_off(a | b) = tile_off(a) +
 // tile_off(b) for disjoint a, b: addresses split into a per-thread part and a
 // per-register part that is uniform across the workgroup.
-__device__ __forceinline__ uint64_t tile_off(uint32_t t, const TileGeom& g) {
+__host__ __device__ __forceinline__ uint64_t tile_off(uint32_t t, const TileGeom& g) {
   const uint32_t rm = (1u << g.R) - 1u, am = (1u << g.hA) - 1u;
   return (uint64_t)(t & rm) | ((uint64_t)((t >> g.R) & am) << g.qA) | ((uint64_t)(t >> (g.R + g.hA)) << g.qB);
 }
@@ -125,7 +133,7 @@ template <>
 struct Swz<2> : Swz<4> {};
 
 template <int ELEM_BYTES>
-__device__ __forceinline__ uint32_t swz(uint32_t t) {
+__host__ __device__ __forceinline__ uint32_t swz(uint32_t t) {
   using Z = Swz<ELEM_BYTES>;
   uint32_t x = 0;
 #pragma unroll
@@ -133,4 +141,14 @@ __device__ __forceinline__ uint32_t swz(uint32_t t) {
   return t ^ x;
 }
 
+// Fill goff / loff for `eb` register bits and LDS entries of lds_bytes.
+template <int LDS_BYTES>
+inline void fill_reg_offsets(TileGeom& g, int eb) {
+  for (int w = 0; w < kMaxWin; ++w)
+    for (int k = 0; k < 16; ++k) {
+      const bool used = k < (1 << eb) && w + eb <= g.tb;
+      g.goff[w][k] = used ? tile_off((uint32_t)k << w, g) : 0;
+      g.loff[w][k] = used ? swz<LDS_BYTES>((uint32_t)k << w) : 0;
+    }
+}
 }  // namespace qk
