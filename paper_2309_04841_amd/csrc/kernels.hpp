@@ -56,9 +56,12 @@ struct C128 {  // complex128: (double re, double im)
     const dvec2 v = {r, i};
     __builtin_nontemporal_store(v, reinterpret_cast<dvec2*>(p) + x);
   }
-  __device__ static __forceinline__ void lput(L* s, uint32_t pos, double r, double i) { s[pos] = make_double2(r, i); }
-  __device__ static __forceinline__ void lget(const L* s, uint32_t pos, double& r, double& i) {
-    const double2 v = s[pos];
+  // LDS accessors take byte offsets (the swizzled position times the entry size)
+  __device__ static __forceinline__ void lput(L* s, uint32_t off, double r, double i) {
+    *reinterpret_cast<double2*>(reinterpret_cast<char*>(s) + off) = make_double2(r, i);
+  }
+  __device__ static __forceinline__ void lget(const L* s, uint32_t off, double& r, double& i) {
+    const double2 v = *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(s) + off);
     r = v.x; i = v.y;
   }
 };
@@ -79,11 +82,11 @@ struct C64 {  // complex64 storage, FP64 arithmetic in registers
     const fvec2 v = {(float)r, (float)i};
     __builtin_nontemporal_store(v, reinterpret_cast<fvec2*>(p) + x);
   }
-  __device__ static __forceinline__ void lput(L* s, uint32_t pos, double r, double i) {
-    s[pos] = make_float2((float)r, (float)i);
+  __device__ static __forceinline__ void lput(L* s, uint32_t off, double r, double i) {
+    *reinterpret_cast<float2*>(reinterpret_cast<char*>(s) + off) = make_float2((float)r, (float)i);
   }
-  __device__ static __forceinline__ void lget(const L* s, uint32_t pos, double& r, double& i) {
-    const float2 v = s[pos];
+  __device__ static __forceinline__ void lget(const L* s, uint32_t off, double& r, double& i) {
+    const float2 v = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(s) + off);
     r = (double)v.x; i = (double)v.y;
   }
 };
@@ -333,22 +336,24 @@ __device__ __forceinline__ void scale_tile(double (&vr)[E], double (&vi)[E], dou
 template <class S, int EB>
 __device__ __forceinline__ void exchange_c(double (&vr)[1 << EB], double (&vi)[1 << EB], typename S::L* lds,
                                            const TileGeom& g, uint32_t tid, int wf, int wt) {
-  // linear swizzle: per-thread part here, per-register part from g.loff
-  const uint32_t pf = swz<S::kLdsBytes>(thr_part<EB>(tid, wf)), pt = swz<S::kLdsBytes>(thr_part<EB>(tid, wt));
+  // linear swizzle in bytes: per-thread part here, per-register part (g.loff,
+  // already in bytes) from the host, so each access costs one XOR
+  const uint32_t pf = swz<S::kLdsBytes>(thr_part<EB>(tid, wf)) * S::kLdsBytes;
+  const uint32_t pt = swz<S::kLdsBytes>(thr_part<EB>(tid, wt)) * S::kLdsBytes;
   if constexpr (S::kSplit) {
     // real parts, then imaginary parts, as 8-byte entries
-    double* d = reinterpret_cast<double*>(lds);
+    char* d = reinterpret_cast<char*>(lds);
 #pragma unroll
-    for (int k = 0; k < (1 << EB); ++k) d[pf ^ g.loff[wf][k]] = vr[k];
+    for (int k = 0; k < (1 << EB); ++k) *reinterpret_cast<double*>(d + (pf ^ g.loff[wf][k])) = vr[k];
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < (1 << EB); ++k) vr[k] = d[pt ^ g.loff[wt][k]];
+    for (int k = 0; k < (1 << EB); ++k) vr[k] = *reinterpret_cast<const double*>(d + (pt ^ g.loff[wt][k]));
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < (1 << EB); ++k) d[pf ^ g.loff[wf][k]] = vi[k];
+    for (int k = 0; k < (1 << EB); ++k) *reinterpret_cast<double*>(d + (pf ^ g.loff[wf][k])) = vi[k];
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < (1 << EB); ++k) vi[k] = d[pt ^ g.loff[wt][k]];
+    for (int k = 0; k < (1 << EB); ++k) vi[k] = *reinterpret_cast<const double*>(d + (pt ^ g.loff[wt][k]));
     __syncthreads();
   } else {
 #pragma unroll

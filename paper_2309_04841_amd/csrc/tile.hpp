@@ -53,8 +53,8 @@ struct TileGeom {
   // Per-register parts of the addresses for register window w, filled on the
   // host (uniform across the workgroup, so the kernels read them with scalar
   // loads instead of recomputing them at every window change):
-  //   goff[w][k] = tile_off(k << w): global offset of register k
-  //   loff[w][k] = swz(k << w): LDS position part of register k
+  //   goff[w][k] = tile_off(k << w): global element offset of register k
+  //   loff[w][k] = swz(k << w) * LDS entry bytes: LDS byte offset part of register k
   uint64_t goff[kMaxWin][16];
   uint32_t loff[kMaxWin][16];
 };
@@ -141,14 +141,14 @@ __host__ __device__ __forceinline__ uint32_t swz(uint32_t t) {
   return t ^ x;
 }
 
-// Fill goff / loff for `eb` register bits and LDS entries of lds_bytes.
+// Fill goff / loff for `eb` register bits and LDS entries of LDS_BYTES.
 template <int LDS_BYTES>
 inline void fill_reg_offsets(TileGeom& g, int eb) {
   for (int w = 0; w < kMaxWin; ++w)
     for (int k = 0; k < 16; ++k) {
       const bool used = k < (1 << eb) && w + eb <= g.tb;
       g.goff[w][k] = used ? tile_off((uint32_t)k << w, g) : 0;
-      g.loff[w][k] = used ? swz<LDS_BYTES>((uint32_t)k << w) : 0;
+      g.loff[w][k] = used ? swz<LDS_BYTES>((uint32_t)k << w) * LDS_BYTES : 0;
     }
 }
 }  // namespace qk
