@@ -1,6 +1,6 @@
 """Throughput benchmark: QAOA expectation evaluations per second on one MI355X.
 
-Workload (default): LABS n=26, p=10, complex128 state, int32 cost vector,
+Workload (default): LABS n=26, p=10, complex128 state, uint16 cost vector,
 linear-ramp schedule (seeded).  One "step" is one full evaluation of the hot
 path: |+>^n generated in-kernel, p layers of phase + mixer sweeps, E fused into
 the last sweep and reduced in FP64.  The cost vector is precomputed once before
@@ -27,7 +27,9 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "QAOA expectation evals/s, LABS n=26 p=10"
 
 CONFIGS = {
-    "labs26": dict(make="C2A", diag="i32"),
+    # LABS energies are integers in [0, sum_k (n-k)^2] (12529 at n=34), so uint16 holds the cost
+    # vector exactly (int32 and float64 are available through --diag)
+    "labs26": dict(make="C2A", diag="u16"),
     "labs31": dict(make="C2B", diag="u16"),
 }
 
@@ -212,6 +214,8 @@ def main(argv=None):
                     help="complex128: 2^14-element tiles when they save a sweep (library tuning knob)")
     ap.add_argument("--fuse-layers", type=int, choices=(0, 1), default=1,
                     help="join adjacent layers in one sweep launch (library tuning knob)")
+    ap.add_argument("--diag", choices=("u16", "i32", "f64"), default=None,
+                    help="cost-vector storage (default: the configuration's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -249,7 +253,9 @@ def main(argv=None):
 
     _lib.set_tuning(_lib.TUNE_WIDE_TILES, args.wide_tiles)
     _lib.set_tuning(_lib.TUNE_FUSE_LAYERS, args.fuse_layers)
-    spec = CONFIGS[args.config]
+    spec = dict(CONFIGS[args.config])
+    if args.diag:
+        spec["diag"] = args.diag
     cfg = getattr(W, spec["make"])()
     n, p = cfg["n"], cfg["p"]
     dev = torch.device("cuda:0")
