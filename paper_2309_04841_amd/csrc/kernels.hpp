@@ -333,6 +333,20 @@ __device__ __forceinline__ void scale_tile(double (&vr)[E], double (&vi)[E], dou
   for (int k = 0; k < E; ++k) { vr[k] *= f; vi[k] *= f; }
 }
 
+// Synchronisation between the write and read halves of a window change.  A
+// change between two windows <= kLocalWin keeps every element in its wave:
+// each wave reads back only what it wrote, so the wave's own LDS writes must
+// complete (lgkmcnt(0)) but no other wave is waited for.  Otherwise the whole
+// workgroup meets at a barrier.
+__device__ __forceinline__ void exchange_sync(bool local) {
+  if (local) {
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt not waited for
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
 template <class S, int EB>
 __device__ __forceinline__ void exchange_c(double (&vr)[1 << EB], double (&vi)[1 << EB], typename S::L* lds,
                                            const TileGeom& g, uint32_t tid, int wf, int wt) {
@@ -340,28 +354,32 @@ __device__ __forceinline__ void exchange_c(double (&vr)[1 << EB], double (&vi)[1
   // already in bytes) from the host, so each access costs one XOR
   const uint32_t pf = swz<S::kLdsBytes>(thr_part<EB>(tid, wf)) * S::kLdsBytes;
   const uint32_t pt = swz<S::kLdsBytes>(thr_part<EB>(tid, wt)) * S::kLdsBytes;
+  // a wave-local change writes and reads only the wave's own positions; the
+  // positions it writes were last read by the same wave, so no barrier is
+  // needed after the reads either
+  const bool local = (wf > wt ? wf : wt) <= kLocalWin;
   if constexpr (S::kSplit) {
     // real parts, then imaginary parts, as 8-byte entries
     char* d = reinterpret_cast<char*>(lds);
 #pragma unroll
     for (int k = 0; k < (1 << EB); ++k) *reinterpret_cast<double*>(d + (pf ^ g.loff[wf][k])) = vr[k];
-    __syncthreads();
+    exchange_sync(local);
 #pragma unroll
     for (int k = 0; k < (1 << EB); ++k) vr[k] = *reinterpret_cast<const double*>(d + (pt ^ g.loff[wt][k]));
-    __syncthreads();
+    exchange_sync(local);
 #pragma unroll
     for (int k = 0; k < (1 << EB); ++k) *reinterpret_cast<double*>(d + (pf ^ g.loff[wf][k])) = vi[k];
-    __syncthreads();
+    exchange_sync(local);
 #pragma unroll
     for (int k = 0; k < (1 << EB); ++k) vi[k] = *reinterpret_cast<const double*>(d + (pt ^ g.loff[wt][k]));
-    __syncthreads();
+    if (!local) __syncthreads();
   } else {
 #pragma unroll
     for (int k = 0; k < (1 << EB); ++k) S::lput(lds, pf ^ g.loff[wf][k], vr[k], vi[k]);
-    __syncthreads();
+    exchange_sync(local);
 #pragma unroll
     for (int k = 0; k < (1 << EB); ++k) S::lget(lds, pt ^ g.loff[wt][k], vr[k], vi[k]);
-    __syncthreads();
+    if (!local) __syncthreads();
   }
 }
 
@@ -608,6 +626,7 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
     for (int k = 0; k < E; ++k) S::store(psi, xb + a.g.goff[w][k], vr[k], vi[k]);
   }
   if constexpr (EXPV) {
+    __syncthreads();  // the tile buffer becomes reduction scratch (the last window change may have been wave-local)
     block_sum2(e_part, n_part, reinterpret_cast<double*>(smem_raw));
     if (tid == 0) {
       double* part = a.partials + (uint64_t)set * a.partials_stride;
@@ -658,6 +677,7 @@ __global__ void __launch_bounds__(512) qaoa_tile_kernel(const SweepArgs a) {
 #pragma unroll
   for (int k = 0; k < E; ++k) S::store(psi, tmap<EB>(tid, k, w), vr[k], vi[k]);
   if (a.flags & F_EXPV) {
+    __syncthreads();  // the tile buffer becomes reduction scratch
     block_sum2(e_part, n_part, reinterpret_cast<double*>(smem_raw));
     if (tid == 0) {
       double* part = a.partials + (uint64_t)set * a.partials_stride;

@@ -68,7 +68,10 @@ int min_passenger_bits(size_t elem_bytes, size_t run_bytes = 128) {
 // Chunk order for one tile: first the top EB bits (the coalesced load window),
 // then the remaining active bits bottom-up; the tile is stored from the last
 // window if that window keeps >= 2^store_min_bits contiguous elements per run,
-// else it is exchanged back to the load window first.
+// else it is exchanged back to the load window first.  The lower chunks use
+// windows w <= qk::kLocalWin where they can: in all such windows the thread
+// bits >= 6 (a thread's wave) map to the same tile bits, so changing between
+// them moves data only within each wave and needs no workgroup barrier.
 qk::TileGeom make_geom(int tb, int R, int hA, int qA, int qB, int act_lo, int eb, int store_min_bits) {
   qk::TileGeom g{};
   g.tb = tb; g.R = R; g.hA = hA; g.qA = qA; g.qB = qB; g.act_lo = act_lo; g.nchunks = 0;
@@ -79,7 +82,7 @@ qk::TileGeom make_geom(int tb, int R, int hA, int qA, int qB, int act_lo, int eb
   const int rhi = lo0;
   while (rlo < rhi) {
     const int chi = std::min(rlo + eb, rhi);
-    const int w = std::min(rlo, top_w);
+    const int w = std::max(chi - eb, std::min(rlo, qk::kLocalWin));  // w <= rlo < top_w, covers [rlo, chi)
     g.chunk[g.nchunks++] = qk::Chunk{(int8_t)w, (int8_t)(rlo - w), (int8_t)(chi - w), 0};
     rlo = chi;
   }

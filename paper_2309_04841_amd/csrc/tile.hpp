@@ -33,6 +33,10 @@ namespace qk {
 
 constexpr int kMaxChunks = 8;
 constexpr int kMaxWin = 11;  // register windows w in [0, 10] (tiles of up to 2^14, >= 8 elements per thread)
+// Windows w <= kLocalWin place every thread bit >= 6 (the wave index within the
+// workgroup) above the register bits, at the same tile bits: a change between
+// two such windows keeps each element in its wave.
+constexpr int kLocalWin = 6;
 
 struct Chunk {
   int8_t w;    // register window: tile bits [w, w+EB)

@@ -250,6 +250,17 @@ def _check_plan(n, plan, elem_bytes, emulate):
                 # the split into per-thread and per-register parts used by the kernels
                 thr = (tid & ((1 << w) - 1)) | ((tid >> w) << (w + eb))
                 assert np.array_equal(tile_off(thr | (k << w), s), tile_off(thr, s) + tile_off(k << w, s))
+            # window changes between windows <= 6 keep every element in its wave
+            # (the kernels skip the workgroup barrier for them)
+            local = sorted(x for x in windows | {s["tb"] - eb} if x <= 6)
+            owner = {}
+            for w in local:
+                t = tmap(tid, k, w, eb)
+                o = np.empty(1 << tb, dtype=np.int64)
+                o[t.ravel()] = np.broadcast_to(tid >> 6, t.shape).ravel()
+                owner[w] = o
+            for w in local[1:]:
+                assert np.array_equal(owner[w], owner[local[0]]), (n, si, local)
     assert sorted(seen) == list(range(n)), "every qubit must be butterflied exactly once per layer"
 
 
@@ -464,3 +475,10 @@ def test_tuning_knobs():
             _lib.set_tuning(*bad)
     with pytest.raises(_lib.QaoaError):
         _lib.get_tuning(7)
+
+
+def test_lower_windows_are_wave_local():
+    # every chunk below the load window uses a window <= 6 in the headline plans
+    for n, sdt in ((26, _lib.QAOA_C128), (31, _lib.QAOA_C64), (20, _lib.QAOA_C128)):
+        for sw in _lib.plan_describe(n, sdt)["sweeps"]:
+            assert all(w <= 6 for (w, _, _) in sw["chunks"][1:]), (n, sw["chunks"])
