@@ -123,6 +123,7 @@ struct DI32 {
   }
   static constexpr double kTableBase = -32768.0;
   static constexpr int kTabLds = 512;  // LDS entries: HI|LO, F1|LO or F3|F2
+  static constexpr bool kPack16 = false;
   using RawT = int32_t;
   __device__ static __forceinline__ double value(RawT r) { return (double)r; }
 };
@@ -139,6 +140,7 @@ struct DU16 {
   __device__ static __forceinline__ int32_t tab_index(int32_t v) { return v; }
   static constexpr double kTableBase = 0.0;
   static constexpr int kTabLds = 512;
+  static constexpr bool kPack16 = true;  // two stored values fit one 32-bit register
   using RawT = int32_t;
   __device__ static __forceinline__ double value(RawT r) { return (double)r; }
 };
@@ -153,6 +155,7 @@ struct DF64 {
   __device__ static __forceinline__ int32_t tab_index(int32_t) { return -1; }
   static constexpr double kTableBase = 0.0;
   static constexpr int kTabLds = 0;
+  static constexpr bool kPack16 = false;
   using RawT = double;
   __device__ static __forceinline__ double value(RawT r) { return r; }
 };
@@ -422,7 +425,7 @@ __device__ __forceinline__ void prepare_pass(double2* tab, const double2* row, u
 
 // Stage HI|LO and decide (workgroup-uniform) whether every value of the tile is
 // covered by it.
-template <class D, int E>
+template <class D, int E, bool PRESTAGED = false>
 __device__ __forceinline__ bool stage_phase_tables(const typename D::RawT (&cv)[E], double2* tab, const double2* row,
                                                    uint32_t tid) {
   int ok = 1;
@@ -430,7 +433,8 @@ __device__ __forceinline__ bool stage_phase_tables(const typename D::RawT (&cv)[
 #pragma unroll
     for (int k = 0; k < E; ++k) ok &= (D::tab_index(cv[k]) >= 0);
   }
-  for (uint32_t e = tid; e < (uint32_t)kTabEntries; e += blockDim.x) tab[e] = row[e];
+  if constexpr (!PRESTAGED)  // else written at kernel start, overlapping the state loads
+    for (uint32_t e = tid; e < (uint32_t)kTabEntries; e += blockDim.x) tab[e] = row[e];
   if constexpr (D::kAlwaysInTable) {
     __syncthreads();
     return true;
@@ -444,13 +448,13 @@ __device__ __forceinline__ bool stage_phase_tables(const typename D::RawT (&cv)[
 // LDS-staged tables (one pass, or two byte-table passes when some int32 value
 // of the workgroup is outside the two-level table; a workgroup-uniform choice);
 // float64 ones evaluate sincos of the angle.
-template <class S, class D, int EB>
+template <class S, class D, int EB, bool PRESTAGED = false>
 __device__ __forceinline__ void phase_from_raw(double (&vr)[1 << EB], double (&vi)[1 << EB],
                                                const typename D::RawT (&cv)[1 << EB], const SweepArgs& a,
                                                const LayerParams& lp, uint32_t tid, double2* tab) {
   constexpr int E = 1 << EB;
   if constexpr (D::kTable) {
-    const bool fast = stage_phase_tables<D, E>(cv, tab, lp.tab, tid);
+    const bool fast = stage_phase_tables<D, E, PRESTAGED>(cv, tab, lp.tab, tid);
     const int npass = fast ? 1 : 2;
     const uint32_t add = fast ? (uint32_t)(-(int32_t)D::kTableBase) : 0u;
 #pragma clang loop unroll(disable)
@@ -586,10 +590,26 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
   }
   if constexpr (EXPV) load_cost<D, EB>(cv, a, base, tid, w_load);
   // complex64 tiles hold the cost values from the start (their loads overlap
-  // the state loads); complex128 ones read them when needed (holding them
-  // through the first gates would spill registers)
+  // the state loads); complex128 ones hold uint16 values packed two per
+  // register, and read wider ones when needed (holding them through the first
+  // gates would spill registers)
   constexpr bool kEarlyCost = !S::kSplit;
+  constexpr bool kPackedCost = FUSE && !kEarlyCost && D::kPack16;
+  uint32_t cpk[kPackedCost ? E / 2 : 1];
   if constexpr (FUSE && kEarlyCost) load_cost<D, EB>(cv, a, base, tid, a.g.chunk[a.g.nchunks - 1].w);
+  if constexpr (kPackedCost) {
+    const int wp = a.g.chunk[a.g.nchunks - 1].w;
+    const uint64_t xb = base + tile_off(thr_part<EB>(tid, wp), a.g);
+    const uint16_t* c16 = reinterpret_cast<const uint16_t*>(a.diag);
+#pragma unroll
+    for (int k = 0; k < E; k += 2)
+      cpk[k / 2] = (uint32_t)c16[xb + a.g.goff[wp][k]] | ((uint32_t)c16[xb + a.g.goff[wp][k + 1]] << 16);
+  }
+  if constexpr (FUSE && D::kTable) {
+    // the next layer's tables go to LDS now, overlapping the state loads
+    const LayerParams lq0 = layer_params(a, set, 1);
+    for (uint32_t e = tid; e < (uint32_t)kTabEntries; e += blockDim.x) tab[e] = lq0.tab[e];
+  }
   if constexpr (PHASE) {
     typename D::RawT pc[E];
     load_cost<D, EB>(pc, a, base, tid, w);
@@ -600,8 +620,13 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
   scale_tile(vr, vi, ipow(lp.ca, nq));
   if constexpr (FUSE) {
     const LayerParams lq = layer_params(a, set, 1);
-    if constexpr (!kEarlyCost) load_cost<D, EB>(cv, a, base, tid, w);
-    phase_from_raw<S, D, EB>(vr, vi, cv, a, lq, tid, tab);
+    if constexpr (kPackedCost) {
+#pragma unroll
+      for (int k = 0; k < E; ++k) cv[k] = (int32_t)((k & 1) ? (cpk[k / 2] >> 16) : (cpk[k / 2] & 0xFFFFu));
+    } else if constexpr (!kEarlyCost) {
+      load_cost<D, EB>(cv, a, base, tid, w);
+    }
+    phase_from_raw<S, D, EB, D::kTable>(vr, vi, cv, a, lq, tid, tab);
     w = apply_mixer<S, EB, true>(vr, vi, lds, a.g, tid, w, lq.tn);  // ends in the load mapping
     scale_tile(vr, vi, ipow(lq.ca, nq));
   }
