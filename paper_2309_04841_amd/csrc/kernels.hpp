@@ -35,8 +35,17 @@ enum : int { F_INIT = 1, F_PHASE = 2, F_EXPV = 4, F_FUSE = 8 };
 // The state is streamed once per sweep: its loads and stores carry the
 // non-temporal hint so they do not displace the cost vector and tables, which
 // are re-read every layer.
+// LDS accesses by byte address.  The tile kernels declare no static LDS, so
+// their dynamic LDS (smem_raw) starts at address 0 and a tile position's byte
+// offset is its LDS address; addressing it directly saves the per-access add of
+// the smem_raw symbol, which the compiler cannot fold.  (A CPU test checks that
+// these kernels have no static LDS.)
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 typedef float fvec2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) double lds_f64;
+typedef __attribute__((address_space(3))) dvec2 lds_f64x2;
+typedef __attribute__((address_space(3))) fvec2 lds_f32x2;
+__device__ __forceinline__ lds_f64* lds_d(uint32_t addr) { return (lds_f64*)(uintptr_t)addr; }
 
 struct C128 {  // complex128: (double re, double im)
   using L = double2;
@@ -57,11 +66,12 @@ struct C128 {  // complex128: (double re, double im)
     __builtin_nontemporal_store(v, reinterpret_cast<dvec2*>(p) + x);
   }
   // LDS accessors take byte offsets (the swizzled position times the entry size)
-  __device__ static __forceinline__ void lput(L* s, uint32_t off, double r, double i) {
-    *reinterpret_cast<double2*>(reinterpret_cast<char*>(s) + off) = make_double2(r, i);
+  __device__ static __forceinline__ void lput(L*, uint32_t off, double r, double i) {
+    const dvec2 v = {r, i};
+    *(lds_f64x2*)(uintptr_t)off = v;
   }
-  __device__ static __forceinline__ void lget(const L* s, uint32_t off, double& r, double& i) {
-    const double2 v = *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(s) + off);
+  __device__ static __forceinline__ void lget(const L*, uint32_t off, double& r, double& i) {
+    const dvec2 v = *(lds_f64x2*)(uintptr_t)off;
     r = v.x; i = v.y;
   }
 };
@@ -82,11 +92,12 @@ struct C64 {  // complex64 storage, FP64 arithmetic in registers
     const fvec2 v = {(float)r, (float)i};
     __builtin_nontemporal_store(v, reinterpret_cast<fvec2*>(p) + x);
   }
-  __device__ static __forceinline__ void lput(L* s, uint32_t off, double r, double i) {
-    *reinterpret_cast<float2*>(reinterpret_cast<char*>(s) + off) = make_float2((float)r, (float)i);
+  __device__ static __forceinline__ void lput(L*, uint32_t off, double r, double i) {
+    const fvec2 v = {(float)r, (float)i};
+    *(lds_f32x2*)(uintptr_t)off = v;
   }
-  __device__ static __forceinline__ void lget(const L* s, uint32_t off, double& r, double& i) {
-    const float2 v = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(s) + off);
+  __device__ static __forceinline__ void lget(const L*, uint32_t off, double& r, double& i) {
+    const fvec2 v = *(lds_f32x2*)(uintptr_t)off;
     r = (double)v.x; i = (double)v.y;
   }
 };
@@ -336,6 +347,7 @@ __device__ __forceinline__ void scale_tile(double (&vr)[E], double (&vi)[E], dou
   for (int k = 0; k < E; ++k) { vr[k] *= f; vi[k] *= f; }
 }
 
+
 // Synchronisation between the write and read halves of a window change.  A
 // change between two windows <= kLocalWin keeps every element in its wave:
 // each wave reads back only what it wrote, so the wave's own LDS writes must
@@ -363,19 +375,19 @@ __device__ __forceinline__ void exchange_c(double (&vr)[1 << EB], double (&vi)[1
   const bool local = (wf > wt ? wf : wt) <= kLocalWin;
   if constexpr (S::kSplit) {
     // real parts, then imaginary parts, as 8-byte entries
-    char* d = reinterpret_cast<char*>(lds);
 #pragma unroll
-    for (int k = 0; k < (1 << EB); ++k) *reinterpret_cast<double*>(d + (pf ^ g.loff[wf][k])) = vr[k];
+    for (int k = 0; k < (1 << EB); ++k) *lds_d(pf ^ g.loff[wf][k]) = vr[k];
     exchange_sync(local);
 #pragma unroll
-    for (int k = 0; k < (1 << EB); ++k) vr[k] = *reinterpret_cast<const double*>(d + (pt ^ g.loff[wt][k]));
+    for (int k = 0; k < (1 << EB); ++k) vr[k] = *lds_d(pt ^ g.loff[wt][k]);
     exchange_sync(local);
 #pragma unroll
-    for (int k = 0; k < (1 << EB); ++k) *reinterpret_cast<double*>(d + (pf ^ g.loff[wf][k])) = vi[k];
+    for (int k = 0; k < (1 << EB); ++k) *lds_d(pf ^ g.loff[wf][k]) = vi[k];
     exchange_sync(local);
 #pragma unroll
-    for (int k = 0; k < (1 << EB); ++k) vi[k] = *reinterpret_cast<const double*>(d + (pt ^ g.loff[wt][k]));
+    for (int k = 0; k < (1 << EB); ++k) vi[k] = *lds_d(pt ^ g.loff[wt][k]);
     if (!local) __syncthreads();
+    (void)lds;
   } else {
 #pragma unroll
     for (int k = 0; k < (1 << EB); ++k) S::lput(lds, pf ^ g.loff[wf][k], vr[k], vi[k]);
@@ -425,6 +437,18 @@ __device__ __forceinline__ void prepare_pass(double2* tab, const double2* row, u
 
 // Stage HI|LO and decide (workgroup-uniform) whether every value of the tile is
 // covered by it.
+// Workgroup-wide OR of a flag: one word per wave after the tables (flags),
+// written by each wave's first active lane, read by everyone after a barrier.
+__device__ __forceinline__ bool block_any(bool v, uint32_t* flags) {
+  const uint64_t m = __ballot(v);
+  const uint32_t wv = threadIdx.x >> 6, nw = (blockDim.x + 63u) >> 6;
+  if (__lane_id() == (uint32_t)__ffsll((unsigned long long)__ballot(1)) - 1u) flags[wv] = m != 0;
+  __syncthreads();
+  uint32_t any = 0;
+  for (uint32_t i = 0; i < nw; ++i) any |= flags[i];
+  return any != 0;
+}
+
 template <class D, int E, bool PRESTAGED = false>
 __device__ __forceinline__ bool stage_phase_tables(const typename D::RawT (&cv)[E], double2* tab, const double2* row,
                                                    uint32_t tid) {
@@ -439,7 +463,7 @@ __device__ __forceinline__ bool stage_phase_tables(const typename D::RawT (&cv)[
     __syncthreads();
     return true;
   } else {
-    return !__syncthreads_or(!ok);
+    return !block_any(!ok, reinterpret_cast<uint32_t*>(tab + kTabEntries));
   }
 }
 
@@ -903,7 +927,8 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_tile_kernel(const AdjArgs a)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   typename S::L* lds = reinterpret_cast<typename S::L*>(smem_raw);
   double2* tab = reinterpret_cast<double2*>(smem_raw + (1u << a.g.tb) * S::kLdsBytes);
-  double* scratch = reinterpret_cast<double*>(smem_raw + (1u << a.g.tb) * S::kLdsBytes + D::kTabLds * sizeof(double2));
+  double* scratch = reinterpret_cast<double*>(smem_raw + (1u << a.g.tb) * S::kLdsBytes + D::kTabLds * sizeof(double2) +
+                                              16 * sizeof(uint32_t));
   const uint32_t tid = threadIdx.x;
   const int w_load = a.g.tb - EB;
   int w = w_load;

@@ -263,7 +263,8 @@ Plan adjoint_plan(int n, size_t state_bytes) { return make_plan(n, state_bytes, 
 template <class S, class D>
 size_t tile_lds_bytes(const qk::TileGeom& g, uint32_t threads, bool phase) {
   const size_t tile = ((size_t)1 << g.tb) * S::kLdsBytes;
-  const size_t tab = (D::kTable && phase) ? D::kTabLds * sizeof(double2) : 0;
+  // tables, then one flag word per wave (16) for the range check
+  const size_t tab = (D::kTable && phase) ? D::kTabLds * sizeof(double2) + 16 * sizeof(uint32_t) : 0;
   return std::max<size_t>(tile + tab, std::max<size_t>(16, 2 * threads) * sizeof(double));
 }
 
@@ -361,7 +362,8 @@ template <class S, class D, bool FIRST, bool PHASE, bool FUSE>
 void launch_adj_f(const qk::AdjArgs& a, uint64_t blocks, hipStream_t st) {
   const uint32_t threads = 1u << (a.g.tb - kEBAdj);
   const size_t tile = ((size_t)1 << a.g.tb) * S::kLdsBytes;
-  const size_t lds = std::max<size_t>(tile + D::kTabLds * sizeof(double2), std::max<size_t>(16, 2 * threads) * sizeof(double));
+  const size_t lds = std::max<size_t>(tile + D::kTabLds * sizeof(double2) + 16 * sizeof(uint32_t),
+                                      std::max<size_t>(16, 2 * threads) * sizeof(double));
   hipLaunchKernelGGL((qk::qaoa_adjoint_kernel<S, D, kEBAdj, FIRST, PHASE, FUSE>), dim3((uint32_t)blocks),
                      dim3(threads), lds, st, with_offsets<S>(a, kEBAdj));
 }
@@ -381,7 +383,7 @@ int launch_adj_d(const qk::AdjArgs& a, int flags, uint64_t blocks, hipStream_t s
 template <class S, class D, int EB>
 void launch_adj_tile_t(const qk::AdjArgs& a, hipStream_t st) {
   const uint32_t threads = 1u << (a.g.tb - EB);
-  const size_t lds = ((size_t)1 << a.g.tb) * S::kLdsBytes + D::kTabLds * sizeof(double2) +
+  const size_t lds = ((size_t)1 << a.g.tb) * S::kLdsBytes + D::kTabLds * sizeof(double2) + 16 * sizeof(uint32_t) +
                      std::max<size_t>(16, 2 * threads) * sizeof(double);
   hipLaunchKernelGGL((qk::qaoa_adjoint_tile_kernel<S, D, EB>), dim3(1), dim3(threads), lds, st, with_offsets<S>(a, EB));
 }

@@ -482,3 +482,32 @@ def test_lower_windows_are_wave_local():
     for n, sdt in ((26, _lib.QAOA_C128), (31, _lib.QAOA_C64), (20, _lib.QAOA_C128)):
         for sw in _lib.plan_describe(n, sdt)["sweeps"]:
             assert all(w <= 6 for (w, _, _) in sw["chunks"][1:]), (n, sw["chunks"])
+
+
+def test_tile_kernels_have_no_static_lds(tmp_path):
+    """The tile kernels address their LDS tiles by absolute byte address, which
+    is right only when their dynamic LDS starts at 0, i.e. they declare no
+    static LDS: read .group_segment_fixed_size from the built code object."""
+    import shutil
+    import subprocess
+    tools = "/opt/rocm/llvm/bin"
+    objcopy, bundler, readelf = (os.path.join(tools, t) for t in ("llvm-objcopy", "clang-offload-bundler", "llvm-readelf"))
+    if not all(os.path.exists(t) for t in (objcopy, bundler, readelf)):
+        pytest.skip("LLVM tools not found")
+    fat, co = tmp_path / "fatbin.bin", tmp_path / "dev.co"
+    subprocess.check_call([objcopy, f"--dump-section=.hip_fatbin={fat}", _lib.LIB_PATH, str(tmp_path / "host.so")])
+    subprocess.check_call([bundler, "--unbundle", "--type=o", f"--input={fat}",
+                           "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", f"--output={co}"])
+    notes = subprocess.check_output([readelf, "--notes", str(co)], text=True)
+    sizes, last = {}, None
+    for line in notes.splitlines():
+        line = line.strip()
+        if line.startswith(".group_segment_fixed_size:"):
+            last = int(line.split(":")[1])
+        elif line.startswith(".name:") and last is not None:
+            sizes[line.split(":", 1)[1].strip()] = last
+            last = None
+    tile = {k: v for k, v in sizes.items() if any(s in k for s in ("qaoa_sweep_kernel", "qaoa_tile_kernel", "qaoa_adjoint"))}
+    assert len(tile) > 20
+    assert all(v == 0 for v in tile.values()), {k: v for k, v in tile.items() if v}
+    shutil.rmtree(tmp_path, ignore_errors=True)
