@@ -63,6 +63,13 @@ def _load():
     lib.oracle_qaoa_evolve.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, P]
     lib.oracle_expectation.argtypes = [ctypes.c_int, P, P, P]
     lib.oracle_qaoa_grad.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P]
+    lib.oracle_apply_xy.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, P]
+    lib.oracle_xy_edges.argtypes = [ctypes.c_int, ctypes.c_int, P]
+    lib.oracle_xy_edges.restype = ctypes.c_int
+    lib.oracle_apply_xy_mixer.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, P]
+    lib.oracle_dicke_state.argtypes = [ctypes.c_int, ctypes.c_int, P]
+    lib.oracle_qaoa_evolve_xy.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int, P]
     _lib = lib
     return lib
 
@@ -179,3 +186,50 @@ def grad(n: int, c, gamma, beta):
     work = np.empty(4 << n, dtype=np.float64)
     _load().oracle_qaoa_grad(n, p, _ptr(c), _ptr(g), _ptr(b), _ptr(out), _ptr(work))
     return float(out[0]), out[1:1 + p].copy(), out[1 + p:].copy()
+
+
+XY_RING, XY_COMPLETE = 1, 2
+
+
+def xy_edges(n: int, kind: int) -> list:
+    """Edges of one XY mixer layer in application order (ring: even, odd, wrap;
+    complete: lexicographic)."""
+    e = np.zeros(2 * n * n + 2, dtype=np.int32)
+    m = _load().oracle_xy_edges(n, kind, _ptr(e))
+    return [(int(e[2 * i]), int(e[2 * i + 1])) for i in range(m)]
+
+
+def apply_xy(n: int, i: int, j: int, beta: float, psi: np.ndarray) -> np.ndarray:
+    """exp(-i beta (X_i X_j + Y_i Y_j)/2) on a copy of psi."""
+    out = np.ascontiguousarray(psi, dtype=np.complex128).copy()
+    _load().oracle_apply_xy(n, int(i), int(j), float(beta), _ptr(out.view(np.float64)))
+    return out
+
+
+def apply_xy_mixer(n: int, kind: int, beta: float, psi: np.ndarray) -> np.ndarray:
+    out = np.ascontiguousarray(psi, dtype=np.complex128).copy()
+    _load().oracle_apply_xy_mixer(n, int(kind), float(beta), _ptr(out.view(np.float64)))
+    return out
+
+
+def dicke_state(n: int, k: int) -> np.ndarray:
+    out = np.empty(1 << n, dtype=np.complex128)
+    _load().oracle_dicke_state(n, int(k), _ptr(out.view(np.float64)))
+    return out
+
+
+def evolve_xy(n: int, c, gamma, beta, kind: int, init: str = "plus", k: int = 0, psi0=None) -> np.ndarray:
+    """QAOA state with an XY mixer; init "plus" (|+>^n), "dicke" (|D^n_k>) or
+    "given" (psi0)."""
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    g = np.ascontiguousarray(np.atleast_1d(gamma), dtype=np.float64)
+    b = np.ascontiguousarray(np.atleast_1d(beta), dtype=np.float64)
+    if g.shape != b.shape or c.shape != (1 << n,):
+        raise ValueError("shape mismatch")
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    code = {"given": 0, "plus": 1, "dicke": 2}[init]
+    if code == 0:
+        psi[:] = psi0
+    _load().oracle_qaoa_evolve_xy(n, len(g), _ptr(c), _ptr(g), _ptr(b), int(kind), code, int(k),
+                                  _ptr(psi.view(np.float64)))
+    return psi

@@ -12,6 +12,10 @@
  *                          applied as in Algorithm 3 (phase, then mixer, layer 1 first)
  *   - mixer                Section 3.2: exp(-i beta sum_i X_i) = prod_i (cos b I - i sin b X_i)
  *   - objective            Section 3.1: E = sum_x |psi_x|^2 c_x
+ *   - XY mixers            Section 3.2: M = sum_<ij> (X_i X_j + Y_i Y_j)/2 over the edges
+ *                          of a ring or a complete graph; one mixer layer is the
+ *                          product of the exact two-qubit exponentials
+ *                          exp(-i beta (X_i X_j + Y_i Y_j)/2) in a fixed edge order
  *   - gradient             dE/dgamma_l, dE/dbeta_l of that objective (the parameters
  *                          an outer optimiser varies, Section 2), by reverse-mode
  *                          (adjoint) differentiation of Algorithm 3
@@ -182,6 +186,86 @@ void oracle_qaoa_evolve(int n, int p, const double *c, const double *gamma,
     for (int l = 0; l < p; ++l) {
         oracle_apply_phase(n, c, gamma[l], psi);
         oracle_apply_mixer(n, beta[l], psi);
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * XY mixers (Section 3.2).  (X_i X_j + Y_i Y_j)/2 maps |01> <-> |10> on the
+ * qubit pair (i, j) and annihilates |00> and |11>, so exp(-i beta (XX+YY)/2)
+ * is the identity on |00>, |11> and the matrix [[cos b, -i sin b],
+ * [-i sin b, cos b]] on the pair of amplitudes (x with bit i = 0, bit j = 1;
+ * the same x with the two bits exchanged).
+ * Edge orders (the paper does not fix them; these are the readings used):
+ *   ring:     (i, i+1) for even i, then for odd i (i + 1 < n), then the wrap
+ *             edge (n-1, 0) when n > 2;
+ *   complete: (i, j), i < j, in lexicographic order.
+ * ------------------------------------------------------------------------- */
+void oracle_apply_xy(int n, int i, int j, double beta, double *psi)
+{
+    const int64_t N = (int64_t)1 << n;
+    const int64_t bi = (int64_t)1 << i, bj = (int64_t)1 << j;
+    const double a = cos(beta), s = sin(beta);
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < N; ++x) {
+        if ((x & bi) || !(x & bj)) continue;      /* x: bit i = 0, bit j = 1 */
+        int64_t y = (x | bi) & ~bj;               /* y: bit i = 1, bit j = 0 */
+        double r0 = psi[2 * x], i0 = psi[2 * x + 1];
+        double r1 = psi[2 * y], i1 = psi[2 * y + 1];
+        psi[2 * x] = a * r0 + s * i1;
+        psi[2 * x + 1] = a * i0 - s * r1;
+        psi[2 * y] = a * r1 + s * i0;
+        psi[2 * y + 1] = a * i1 - s * r0;
+    }
+}
+
+/* Edge list of one XY mixer layer in application order: kind 1 = ring,
+ * kind 2 = complete.  Writes pairs into edges[2 * m], returns the count. */
+int oracle_xy_edges(int n, int kind, int32_t *edges)
+{
+    int m = 0;
+    if (kind == 1) {
+        for (int par = 0; par < 2; ++par)
+            for (int i = par; i + 1 < n; i += 2) { edges[2 * m] = i; edges[2 * m + 1] = i + 1; ++m; }
+        if (n > 2) { edges[2 * m] = n - 1; edges[2 * m + 1] = 0; ++m; }
+    } else if (kind == 2) {
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) { edges[2 * m] = i; edges[2 * m + 1] = j; ++m; }
+    }
+    return m;
+}
+
+void oracle_apply_xy_mixer(int n, int kind, double beta, double *psi)
+{
+    int32_t *edges = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * (size_t)n + 8);
+    const int m = oracle_xy_edges(n, kind, edges);
+    for (int e = 0; e < m; ++e) oracle_apply_xy(n, edges[2 * e], edges[2 * e + 1], beta, psi);
+    free(edges);
+}
+
+/* Dicke state |D^n_k>: equal amplitude C(n,k)^{-1/2} on every x of Hamming
+ * weight k, zero elsewhere. */
+void oracle_dicke_state(int n, int k, double *psi)
+{
+    const int64_t N = (int64_t)1 << n;
+    double cnk = 1.0;
+    for (int t = 1; t <= k; ++t) cnk = cnk * (double)(n - k + t) / (double)t;
+    const double a = 1.0 / sqrt(cnk);
+    for (int64_t x = 0; x < N; ++x) {
+        psi[2 * x] = (__builtin_popcountll((unsigned long long)x) == k) ? a : 0.0;
+        psi[2 * x + 1] = 0.0;
+    }
+}
+
+/* QAOA with an XY mixer: start (init 0: given psi; 1: |+>^n; 2: Dicke |D^n_k>),
+ * then for each layer the phase and the XY mixer layer. */
+void oracle_qaoa_evolve_xy(int n, int p, const double *c, const double *gamma, const double *beta, int kind,
+                           int init, int k, double *psi)
+{
+    if (init == 1) oracle_plus_state(n, psi);
+    if (init == 2) oracle_dicke_state(n, k, psi);
+    for (int l = 0; l < p; ++l) {
+        oracle_apply_phase(n, c, gamma[l], psi);
+        oracle_apply_xy_mixer(n, kind, beta[l], psi);
     }
 }
 

@@ -45,3 +45,24 @@ def maxcut_p1_closed_form(n, edges, gamma, beta):
                 - 0.25 * np.sin(2 * beta) ** 2 * np.cos(gamma) ** (du + dv - 2 * lam)
                 * (1 - np.cos(2 * gamma) ** lam))
     return tot
+
+
+def xy_generator(n, i, j):
+    """(X_i X_j + Y_i Y_j)/2 as a dense 2^n x 2^n matrix (Kronecker products)."""
+    X = np.array([[0.0, 1.0], [1.0, 0.0]], dtype=np.complex128)
+    Y = np.array([[0.0, -1.0j], [1.0j, 0.0]], dtype=np.complex128)
+
+    def op(mats):  # mats: {qubit: 2x2}; qubit n-1 is the leftmost factor
+        out = np.eye(1, dtype=np.complex128)
+        for q in range(n - 1, -1, -1):
+            out = np.kron(out, mats.get(q, np.eye(2)))
+        return out
+    return 0.5 * (op({i: X, j: X}) + op({i: Y, j: Y}))
+
+
+def xy_layer_dense(n, edges, beta):
+    """Product of scipy expm(-i beta G_e) over `edges`, first edge applied first."""
+    U = np.eye(1 << n, dtype=np.complex128)
+    for i, j in edges:
+        U = scipy.linalg.expm(-1j * beta * xy_generator(n, i, j)) @ U
+    return U

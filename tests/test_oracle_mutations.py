@@ -14,6 +14,7 @@ import oracle
 import test_oracle_diag as D
 import test_oracle_evolve as V
 import test_oracle_grad as G
+import test_oracle_xy as XY
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
 
@@ -39,6 +40,15 @@ MUTANTS = {
         "        out[1 + p + l] = 2.0 * sb;\n        oracle_apply_mixer(n, -beta[l], psi);\n        oracle_apply_mixer(n, -beta[l], lam);\n        double sg = 0.0;",
         "        out[1 + p + l] = 2.0 * sb;\n        double sg = 0.0;"),
     # adjoint: conjugation on the wrong factor (sign of the beta term)
+    # XY gate pairs x with bit j set but forgets to clear it in the partner
+    "xy_partner_keeps_bit_j": ("int64_t y = (x | bi) & ~bj;               /* y: bit i = 1, bit j = 0 */",
+                               "int64_t y = (x | bi);                     /* y: bit i = 1, bit j = 0 */"),
+    # ring order: odd edges before even edges
+    "xy_ring_parity_order": ("for (int par = 0; par < 2; ++par)", "for (int par = 1; par >= 0; --par)"),
+    "xy_complete_reverse_order": ("for (int j = i + 1; j < n; ++j) { edges[2 * m] = i;",
+                                  "for (int j = n - 1; j > i; --j) { edges[2 * m] = i;"),
+    "dicke_wrong_weight": ("psi[2 * x] = (__builtin_popcountll((unsigned long long)x) == k) ? a : 0.0;",
+                           "psi[2 * x] = (__builtin_popcountll((unsigned long long)x) == k + 1) ? a : 0.0;"),
     "grad_beta_conjugate": ("sq += lam[2 * x] * psi[2 * y + 1] - lam[2 * x + 1] * psi[2 * y];",
                             "sq += lam[2 * x + 1] * psi[2 * y] - lam[2 * x] * psi[2 * y + 1];"),
 }
@@ -55,6 +65,9 @@ PINS = [
     lambda: V.test_norm_preserved_and_beta_zero_mean(4),
     lambda: G.test_grad_matches_central_differences(5, 3, 1),
     G.test_p1_maxcut_gradient_closed_form,
+    lambda: XY.test_xy_layer_matches_dense_expm(5, oracle.XY_RING, XY.ring_order),
+    lambda: XY.test_xy_layer_matches_dense_expm(4, oracle.XY_COMPLETE, XY.complete_order),
+    lambda: XY.test_dicke_state(6, 3),
 ]
 
 
