@@ -62,6 +62,10 @@ enum { QAOA_C64 = 0, QAOA_C128 = 1 };
 /* Cost-vector dtypes. */
 enum { QAOA_DIAG_F64 = 0, QAOA_DIAG_I32 = 1, QAOA_DIAG_U16 = 2 };
 
+/* Mixers (Section 3.2) and initial states for qaoa_evolve_xy. */
+enum { QAOA_MIXER_X = 0, QAOA_MIXER_XY_RING = 1, QAOA_MIXER_XY_COMPLETE = 2 };
+enum { QAOA_INIT_GIVEN = 0, QAOA_INIT_PLUS = 1, QAOA_INIT_DICKE = 2 };
+
 /* Operations for qaoa_workspace_bytes. */
 enum { QAOA_OP_PRECOMPUTE = 0, QAOA_OP_EVOLVE = 1, QAOA_OP_EXPECTATION = 2, QAOA_OP_GRAD = 3 };
 
@@ -266,6 +270,30 @@ int qaoa_server_submit(qaoa_server *s, int problem_id, int kind, int state_dtype
 int qaoa_server_wait(qaoa_server *s, int64_t ticket, double *out, int out_len, double *latency_s);
 int qaoa_server_stats_get(qaoa_server *s, qaoa_server_stats *out);
 int qaoa_server_reset_stats(qaoa_server *s);
+
+/*
+ * qaoa_evolve_xy -- QAOA with a Hamming-weight-preserving XY mixer (Section 3.2):
+ * M = sum over the edges <i,j> of a ring or of the complete graph on the qubits
+ * of (X_i X_j + Y_i Y_j)/2.  Each layer applies exp(-i gamma_l C) (Section 3.1),
+ * then the product of the exact two-qubit gates exp(-i beta_l (X_i X_j +
+ * Y_i Y_j)/2) in a fixed edge order: ring (i, i+1) for even i, then odd i, then
+ * (n-1, 0) when n > 2; complete graph (i, j), i < j, lexicographic.  (The paper
+ * fixes neither the order of these non-commuting terms nor an initial state.)
+ *   mixer      QAOA_MIXER_XY_RING or QAOA_MIXER_XY_COMPLETE; 2 <= n <= 30.
+ *   init       QAOA_INIT_GIVEN (d_state holds the start), QAOA_INIT_PLUS (|+>^n),
+ *              QAOA_INIT_DICKE (the Dicke state of Hamming weight k, 0 <= k <= n).
+ *   other arguments as in qaoa_evolve; d_out (E, sum |psi|^2) may be NULL.
+ * Workspace: qaoa_xy_workspace_bytes.  Same stream semantics as qaoa_evolve.
+ */
+int qaoa_evolve_xy(int n, int p, const double *gamma, const double *beta, int mixer, const void *d_diag,
+                   int diag_dtype, double diag_offset, size_t diag_bytes, void *d_state, int state_dtype,
+                   size_t state_bytes, int init, int k, double *d_out, void *d_work, size_t work_bytes,
+                   void *stream);
+int qaoa_xy_workspace_bytes(int n, int mixer, int state_dtype, size_t *bytes);
+/* Diagnostic: the XY sweep plan.  Writes [S, EB, single] then per sweep
+ * tb, R, hA, qA, qB, ngates and ngates (i, j) tile-bit pairs (the tile-bit
+ * mapping as in qaoa_plan_describe).  Returns the count or -QAOA_ERR_INVALID. */
+int qaoa_xy_plan_describe(int n, int mixer, int state_dtype, int *out, int cap);
 
 /*
  * qaoa_plan_describe -- diagnostic: the HBM sweep plan used for n qubits.

@@ -25,7 +25,7 @@ EXPORTS = ("qaoa_version", "qaoa_last_error", "qaoa_workspace_bytes", "qaoa_prec
            "qaoa_batch_workspace_bytes", "qaoa_grad_workspace_bytes", "qaoa_server_create",
            "qaoa_server_destroy", "qaoa_server_add_problem", "qaoa_server_submit", "qaoa_server_wait",
            "qaoa_server_stats_get", "qaoa_server_reset_stats", "qaoa_schedule_describe", "qaoa_set_tuning",
-           "qaoa_get_tuning")
+           "qaoa_get_tuning", "qaoa_evolve_xy", "qaoa_xy_workspace_bytes", "qaoa_xy_plan_describe")
 
 _STATUS_NAMES = {0: "QAOA_OK", 1: "QAOA_ERR_INVALID", 2: "QAOA_ERR_RANGE", 3: "QAOA_ERR_NOMEM",
                  4: "QAOA_ERR_DEVICE", 5: "QAOA_ERR_UNSUPPORTED"}
@@ -71,6 +71,12 @@ def _load() -> ctypes.CDLL:
     lib.qaoa_evolve_batch.argtypes = [I, I, I, P, P, P, I, D, SZ, P, I, SZ, I, P, I, P, SZ, P]
     lib.qaoa_batch_workspace_bytes.restype = I
     lib.qaoa_batch_workspace_bytes.argtypes = [I, I, I, I, I, ctypes.POINTER(SZ)]
+    lib.qaoa_evolve_xy.restype = I
+    lib.qaoa_evolve_xy.argtypes = [I, I, P, P, I, P, I, D, SZ, P, I, SZ, I, I, P, P, SZ, P]
+    lib.qaoa_xy_workspace_bytes.restype = I
+    lib.qaoa_xy_workspace_bytes.argtypes = [I, I, I, ctypes.POINTER(SZ)]
+    lib.qaoa_xy_plan_describe.restype = I
+    lib.qaoa_xy_plan_describe.argtypes = [I, I, I, P, I]
     return lib
 
 
@@ -159,6 +165,31 @@ def plan_describe(n: int, state_dtype: int = QAOA_C128, elem_bytes: int = 0, kin
 
 
 F_INIT, F_PHASE, F_EXPV, F_FUSE = 1, 2, 4, 8
+
+MIXER_X, MIXER_XY_RING, MIXER_XY_COMPLETE = 0, 1, 2
+INIT_GIVEN, INIT_PLUS, INIT_DICKE = 0, 1, 2
+MIXER_NAMES = {"x": MIXER_X, "xy_ring": MIXER_XY_RING, "xy_complete": MIXER_XY_COMPLETE}
+
+
+def xy_plan_describe(n: int, mixer: int, state_dtype: int = QAOA_C128) -> dict:
+    """The XY sweep plan: {'eb', 'single', 'sweeps': [{'tb','R','hA','qA','qB','gates': [(i, j), ...]}]}
+    with gates as tile-bit pairs, in the order they are applied."""
+    need = lib.qaoa_xy_plan_describe(n, mixer, state_dtype, None, 0)
+    if need < 0:
+        check(-need)
+    buf = (ctypes.c_int * need)()
+    lib.qaoa_xy_plan_describe(n, mixer, state_dtype, buf, need)
+    v = list(buf)
+    ns, eb, single = v[0], v[1], v[2]
+    i = 3
+    sweeps = []
+    for _ in range(ns):
+        tb, R, hA, qA, qB, ng = v[i:i + 6]
+        i += 6
+        gates = [(v[i + 2 * e], v[i + 2 * e + 1]) for e in range(ng)]
+        i += 2 * ng
+        sweeps.append(dict(tb=tb, R=R, hA=hA, qA=qA, qB=qB, gates=gates))
+    return dict(eb=eb, single=bool(single), sweeps=sweeps)
 
 
 TUNE_WIDE_TILES, TUNE_FUSE_LAYERS = 0, 1
@@ -302,6 +333,30 @@ def qaoa_grad(n: int, gamma, beta, diag: torch.Tensor, state: torch.Tensor, adj:
                         _dev_ptr(state), _dev_ptr(adj), sdt, _nbytes(state), _dev_ptr(out), _dev_ptr(work),
                         _nbytes(work), _stream(state.device)))
     return out
+
+
+def xy_workspace_bytes(n: int, mixer: int, state_dtype: int) -> int:
+    out = ctypes.c_size_t(0)
+    check(lib.qaoa_xy_workspace_bytes(n, mixer, state_dtype, ctypes.byref(out)))
+    return int(out.value)
+
+
+def qaoa_evolve_xy(n: int, gamma, beta, diag: torch.Tensor, state: torch.Tensor, mixer: int | str = MIXER_XY_RING,
+                   init: int = INIT_PLUS, k: int = 0, diag_offset: float = 0.0, out: torch.Tensor | None = None,
+                   work: torch.Tensor | None = None) -> None:
+    """p layers of phase and XY mixer (ring or complete graph) in place on ``state``,
+    which starts as |+>^n (INIT_PLUS), the Dicke state of weight k (INIT_DICKE), or
+    as given (INIT_GIVEN); ``out`` (float64[2], device) receives (E, sum |psi|^2)."""
+    p = len(gamma)
+    if len(beta) != p:
+        raise ValueError("gamma and beta differ in length")
+    code = MIXER_NAMES[mixer] if isinstance(mixer, str) else int(mixer)
+    sdt, ddt = state_dtype_code(state), diag_dtype_code(diag)
+    if work is None:
+        work = torch.empty(max(16, xy_workspace_bytes(n, code, sdt)), dtype=torch.uint8, device=state.device)
+    check(lib.qaoa_evolve_xy(n, p, _f64(gamma), _f64(beta), code, _dev_ptr(diag), ddt, float(diag_offset),
+                             _nbytes(diag), _dev_ptr(state), sdt, _nbytes(state), int(init), int(k), _dev_ptr(out),
+                             _dev_ptr(work), _nbytes(work), _stream(state.device)))
 
 
 def batch_workspace_bytes(n: int, p: int, batch: int, state_dtype: int, diag_dtype: int) -> int:

@@ -919,6 +919,120 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_kernel(const AdjArgs a) {
   }
 }
 
+// ----------------------------------------------------------------------------
+// XY mixers (Section 3.2): M = sum over edges <i,j> of (X_i X_j + Y_i Y_j)/2.
+// exp(-i beta (X_i X_j + Y_i Y_j)/2) leaves |00>, |11> of the pair unchanged and
+// rotates the amplitude pair (bit i = 0, bit j = 1) / (bit i = 1, bit j = 0)
+// by [[cos b, -i sin b], [-i sin b, cos b]], the same 2x2 as the X gate.  The
+// gates of an edge sequence do not commute, so a sweep applies a contiguous
+// run of the sequence, in order, to a tile that holds all their qubits; the
+// tile lives in LDS (complex128 entries) while the gates run.
+// ----------------------------------------------------------------------------
+constexpr int kMaxXyGates = 128;
+
+struct XyArgs {
+  SweepArgs s;       // state, cost vector, tables, geometry, parameter rows, partials, flags
+  int ngates;        // gates per layer in this launch, applied in order
+  int dicke_k;       // F_INIT: -1 = |+>^n (amp0 everywhere); k >= 0 = amp0 on Hamming weight k
+  int8_t gate[kMaxXyGates][2];  // tile-bit pairs (i, j)
+};
+
+// x with zero bits inserted at positions lo < hi.
+__device__ __forceinline__ uint32_t insert_two_zeros(uint32_t q, int lo, int hi) {
+  q = ((q >> lo) << (lo + 1)) | (q & ((1u << lo) - 1u));
+  return ((q >> hi) << (hi + 1)) | (q & ((1u << hi) - 1u));
+}
+
+// One launch: for each of nlayers layers (several only when the tile is the
+// whole state): [phase] then the gate list; flags F_INIT / F_PHASE / F_EXPV as
+// in the X mixer sweeps.  Tile in LDS as double2, 2^tb entries, natural order.
+template <class S, class D, int EB>
+__global__ void __launch_bounds__(512) qaoa_xy_kernel(const XyArgs a) {
+  constexpr int E = 1 << EB;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const SweepArgs& sa = a.s;
+  const TileGeom& g = sa.g;
+  double2* tile = reinterpret_cast<double2*>(smem_raw);
+  double2* tab = reinterpret_cast<double2*>(smem_raw + ((size_t)1 << g.tb) * sizeof(double2));
+  const uint32_t tid = threadIdx.x;
+  const uint64_t base = block_base(xcd_block(blockIdx.x, gridDim.x), g);
+  const uint32_t set = blockIdx.y;
+  void* psi = reinterpret_cast<char*>(sa.psi) + (uint64_t)set * sa.set_stride_bytes;
+  const int w = g.tb - EB;  // the coalesced load mapping
+  const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), g);
+  double vr[E], vi[E];
+  if (sa.flags & F_INIT) {
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const uint64_t x = xb + g.goff[w][k];
+      const bool on = a.dicke_k < 0 || __popcll(x) == a.dicke_k;
+      vr[k] = on ? sa.amp0 : 0.0;
+      vi[k] = 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < E; ++k) S::load(psi, xb + g.goff[w][k], vr[k], vi[k]);
+  }
+  typename D::RawT cv[E];
+  if (sa.flags & (F_PHASE | F_EXPV)) load_cost<D, EB>(cv, sa, base, tid, w);
+  const uint32_t npairs = 1u << (g.tb - 2);
+  for (int l = 0; l < sa.nlayers; ++l) {
+    const LayerParams lp = layer_params(sa, set, l);
+    if (l > 0) {
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const double2 v = tile[tmap<EB>(tid, k, w)];
+        vr[k] = v.x; vi[k] = v.y;
+      }
+      __syncthreads();  // table reads of the previous layer are done before restaging
+    }
+    if (sa.flags & F_PHASE) phase_from_raw<S, D, EB>(vr, vi, cv, sa, lp, tid, tab);
+#pragma unroll
+    for (int k = 0; k < E; ++k) tile[tmap<EB>(tid, k, w)] = make_double2(vr[k], vi[k]);
+    __syncthreads();
+    for (int e = 0; e < a.ngates; ++e) {
+      const int ti = a.gate[e][0], tj = a.gate[e][1];
+      const int lo = ti < tj ? ti : tj, hi = ti < tj ? tj : ti;
+      for (uint32_t q = tid; q < npairs; q += blockDim.x) {
+        const uint32_t x = insert_two_zeros(q, lo, hi);
+        const uint32_t x0 = x | (1u << tj), x1 = x | (1u << ti);
+        double2 u = tile[x0], v = tile[x1];
+        rx_pair(u.x, u.y, v.x, v.y, lp.ca, lp.sb);
+        tile[x0] = u;
+        tile[x1] = v;
+      }
+      __syncthreads();
+    }
+  }
+  if (sa.nlayers > 0) {  // else the registers still hold the loaded (or generated) state
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const double2 v = tile[tmap<EB>(tid, k, w)];
+      vr[k] = v.x; vi[k] = v.y;
+    }
+  }
+  double e_part = 0.0, n_part = 0.0;
+  if (sa.flags & F_EXPV) {
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const double pr = vr[k] * vr[k] + vi[k] * vi[k];
+      e_part += pr * (D::value(cv[k]) + sa.diag_offset);
+      n_part += pr;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < E; ++k) S::store(psi, xb + g.goff[w][k], vr[k], vi[k]);
+  if (sa.flags & F_EXPV) {
+    __syncthreads();  // the tile buffer becomes reduction scratch
+    block_sum2(e_part, n_part, reinterpret_cast<double*>(smem_raw));
+    if (tid == 0) {
+      double* part = sa.partials + (uint64_t)set * sa.partials_stride;
+      part[2 * (uint64_t)blockIdx.x] = e_part;
+      part[2 * (uint64_t)blockIdx.x + 1] = n_part;
+    }
+  }
+}
+
 // Whole state in one tile: lambda = c psi, then layers nlayers-1 .. 0 in reverse;
 // layer l's (beta term, gamma term) go to partials + l * layer_partials_stride.
 template <class S, class D, int EB>

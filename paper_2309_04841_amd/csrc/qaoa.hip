@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <set>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -254,6 +255,133 @@ constexpr int kEBAdj = 3;
 Plan adjoint_plan(int n, size_t state_bytes) { return make_plan(n, state_bytes, kEBAdj); }
 
 // ---------------------------------------------------------------------------
+// XY mixer plans (Section 3.2).  One layer is an ordered edge sequence
+// (ring: (i, i+1) for even i, then odd i, then the wrap edge (n-1, 0) when
+// n > 2; complete graph: (i, j), i < j, lexicographic).  A sweep applies a
+// contiguous run of it to tiles that hold all the run's qubits plus the
+// passenger bits [0, pmin) for coalescing; the tile's bits must form the run
+// [0, R) and at most two more contiguous segments (the tile geometry).
+// ---------------------------------------------------------------------------
+constexpr int kXyTileBits = 12;  // 2^12 complex128 LDS entries = 64 KiB
+
+std::vector<std::pair<int, int>> xy_edges(int n, int mixer) {
+  std::vector<std::pair<int, int>> e;
+  if (mixer == QAOA_MIXER_XY_RING) {
+    for (int par = 0; par < 2; ++par)
+      for (int i = par; i + 1 < n; i += 2) e.emplace_back(i, i + 1);
+    if (n > 2) e.emplace_back(n - 1, 0);
+  } else {
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) e.emplace_back(i, j);
+  }
+  return e;
+}
+
+struct XySweep {
+  qk::TileGeom g;
+  std::vector<std::pair<int, int>> gates;  // tile bits
+};
+struct XyPlan {
+  bool single;
+  int eb;
+  std::vector<XySweep> sweeps;
+};
+
+// Runs of consecutive set bits in `bits` (sorted): (start, length).
+std::vector<std::pair<int, int>> bit_runs(const std::vector<int>& bits) {
+  std::vector<std::pair<int, int>> r;
+  for (int b : bits) {
+    if (!r.empty() && r.back().first + r.back().second == b) ++r.back().second;
+    else r.emplace_back(b, 1);
+  }
+  return r;
+}
+
+// Tile bits of a qubit set: the set plus [0, pmin); fits if at most tbmax bits
+// forming the run from 0 and at most two more runs.
+bool xy_fits(const std::set<int>& q, int pmin, int tbmax) {
+  std::set<int> b(q);
+  for (int i = 0; i < pmin; ++i) b.insert(i);
+  if ((int)b.size() > tbmax) return false;
+  const auto r = bit_runs(std::vector<int>(b.begin(), b.end()));
+  return (int)r.size() - (r.front().first == 0 ? 1 : 0) <= 2;
+}
+
+XySweep xy_sweep(int n, const std::set<int>& q, const std::vector<std::pair<int, int>>& edges, int pmin, int tbmax) {
+  std::set<int> b(q);
+  for (int i = 0; i < pmin; ++i) b.insert(i);
+  for (int x = 0; (int)b.size() < tbmax && x < n; ++x) b.insert(x);  // pad: extend the run from 0
+  const std::vector<int> bits(b.begin(), b.end());
+  auto runs = bit_runs(bits);
+  XySweep sw{};
+  qk::TileGeom& g = sw.g;
+  g.tb = (int)bits.size();
+  g.R = runs.front().first == 0 ? runs.front().second : 0;
+  if (g.R > 0) runs.erase(runs.begin());
+  if (runs.empty()) { g.hA = 0; g.qA = g.qB = n; }
+  else if (runs.size() == 1) { g.hA = runs[0].second; g.qA = runs[0].first; g.qB = g.qA + g.hA; }
+  else { g.hA = runs[0].second; g.qA = runs[0].first; g.qB = runs[1].first; }
+  g.act_lo = 0;
+  g.nchunks = 0;
+  g.w_store = 0;
+  auto tbit = [&](int x) {
+    return (int)(std::lower_bound(bits.begin(), bits.end(), x) - bits.begin());  // bits sorted = tile bit order
+  };
+  for (const auto& e : edges) sw.gates.emplace_back(tbit(e.first), tbit(e.second));
+  return sw;
+}
+
+XyPlan make_xy_plan(int n, int mixer, size_t elem_bytes) {
+  XyPlan pl;
+  const auto edges = xy_edges(n, mixer);
+  if (n <= kXyTileBits) {
+    pl.single = true;
+    pl.eb = std::min(kEB, n);
+    std::set<int> all;
+    for (int i = 0; i < n; ++i) all.insert(i);
+    pl.sweeps.push_back(xy_sweep(n, all, edges, 0, n));
+    return pl;
+  }
+  pl.single = false;
+  pl.eb = kEB;
+  const int pmin = min_passenger_bits(elem_bytes);
+  // Gates on disjoint qubits commute, so a sweep may take any gate whose
+  // earlier neighbours (earlier gates sharing a qubit) are all applied.  One
+  // pass in the fixed order per sweep: a gate whose qubits fit the tile and
+  // are not blocked is applied; otherwise its qubits become blocked, since
+  // every later gate on them must follow it.  The first pending gate is
+  // always applied, so every sweep makes progress.
+  std::vector<char> done(edges.size(), 0);
+  size_t remaining = edges.size();
+  while (remaining > 0) {
+    std::set<int> q;
+    std::vector<char> blocked(n, 0);
+    std::vector<std::pair<int, int>> run;
+    for (size_t e = 0; e < edges.size(); ++e) {
+      if (done[e]) continue;
+      const int i = edges[e].first, j = edges[e].second;
+      bool ok = !blocked[i] && !blocked[j];
+      if (ok) {
+        std::set<int> q2(q);
+        q2.insert(i);
+        q2.insert(j);
+        ok = xy_fits(q2, pmin, kXyTileBits);
+        if (ok) q.swap(q2);
+      }
+      if (ok) {
+        done[e] = 1;
+        --remaining;
+        run.push_back(edges[e]);
+      } else {
+        blocked[i] = blocked[j] = 1;
+      }
+    }
+    pl.sweeps.push_back(xy_sweep(n, q, run, pmin, kXyTileBits));
+  }
+  return pl;
+}
+
+// ---------------------------------------------------------------------------
 // typed launchers
 // ---------------------------------------------------------------------------
 // LDS bytes of a tile kernel: the tile, the phase tables when the launch
@@ -356,6 +484,40 @@ void launch_tile_s(const qk::SweepArgs& a, int diag_dtype, int eb, uint32_t sets
 void launch_tile(const qk::SweepArgs& a, int state_dtype, int diag_dtype, int eb, uint32_t sets, hipStream_t st) {
   if (state_dtype == QAOA_C128) launch_tile_s<qk::C128>(a, diag_dtype, eb, sets, st);
   else launch_tile_s<qk::C64>(a, diag_dtype, eb, sets, st);
+}
+
+// XY mixer launches: tile of 2^tb complex128 LDS entries + phase tables + flags.
+template <class S, class D, int EB>
+void launch_xy_t(const qk::XyArgs& a, uint64_t blocks, uint32_t sets, hipStream_t st) {
+  const uint32_t threads = 1u << (a.s.g.tb - EB);
+  const size_t tile = ((size_t)1 << a.s.g.tb) * sizeof(double2);
+  const size_t lds = std::max<size_t>(tile + qk::kTabEntries * sizeof(double2) + 16 * sizeof(uint32_t),
+                                      std::max<size_t>(16, 2 * threads) * sizeof(double));
+  qk::XyArgs b = a;
+  qk::fill_reg_offsets<16>(b.s.g, EB);
+  hipLaunchKernelGGL((qk::qaoa_xy_kernel<S, D, EB>), dim3((uint32_t)blocks, sets), dim3(threads), lds, st, b);
+}
+
+template <class S, class D>
+void launch_xy_d(const qk::XyArgs& a, int eb, uint64_t blocks, uint32_t sets, hipStream_t st) {
+  switch (eb) {
+    case 1: launch_xy_t<S, D, 1>(a, blocks, sets, st); break;
+    case 2: launch_xy_t<S, D, 2>(a, blocks, sets, st); break;
+    case 3: launch_xy_t<S, D, 3>(a, blocks, sets, st); break;
+    default: launch_xy_t<S, D, 4>(a, blocks, sets, st); break;
+  }
+}
+
+void launch_xy(const qk::XyArgs& a, int sdt, int ddt, int eb, uint64_t blocks, uint32_t sets, hipStream_t st) {
+  if (sdt == QAOA_C128) {
+    if (ddt == QAOA_DIAG_I32) launch_xy_d<qk::C128, qk::DI32>(a, eb, blocks, sets, st);
+    else if (ddt == QAOA_DIAG_U16) launch_xy_d<qk::C128, qk::DU16>(a, eb, blocks, sets, st);
+    else launch_xy_d<qk::C128, qk::DF64>(a, eb, blocks, sets, st);
+  } else {
+    if (ddt == QAOA_DIAG_I32) launch_xy_d<qk::C64, qk::DI32>(a, eb, blocks, sets, st);
+    else if (ddt == QAOA_DIAG_U16) launch_xy_d<qk::C64, qk::DU16>(a, eb, blocks, sets, st);
+    else launch_xy_d<qk::C64, qk::DF64>(a, eb, blocks, sets, st);
+  }
 }
 
 template <class S, class D, bool FIRST, bool PHASE, bool FUSE>
@@ -1059,6 +1221,160 @@ int qaoa_schedule_describe(int kind, int n, int p, int state_dtype, int init, in
       if (out && i < cap) out[i] = v[j];
   }
   return i;
+}
+
+static size_t xy_work_bytes(int n, int mixer, int sdt) {
+  const XyPlan pl = make_xy_plan(n, mixer, state_elem_bytes(sdt));
+  uint64_t blocks = 1;
+  for (const auto& sw : pl.sweeps) blocks = std::max(blocks, plan_blocks(n, sw.g));
+  const size_t stride = 2 * std::max<uint64_t>(blocks, kExpectBlocks);
+  const size_t rows = qk::kPrepRows;
+  return sizeof(double) * stride + ((qk::kParamRow * sizeof(double) * rows + 255) / 256) * 256 +
+         rows * qk::kTabRow * sizeof(double2) + sizeof(double) * 2 * kReduceChunks;
+}
+
+static int validate_xy(int n, int mixer, int state_dtype) {
+  if (mixer != QAOA_MIXER_XY_RING && mixer != QAOA_MIXER_XY_COMPLETE)
+    return fail(QAOA_ERR_INVALID, "mixer must be QAOA_MIXER_XY_RING or QAOA_MIXER_XY_COMPLETE, got %d", mixer);
+  if (n < 2 || n > 30) return fail(QAOA_ERR_INVALID, "n=%d out of range [2, 30] for XY mixers", n);
+  if (!valid_state_dtype(state_dtype)) return fail(QAOA_ERR_INVALID, "bad state dtype %d", state_dtype);
+  return QAOA_OK;
+}
+
+int qaoa_xy_workspace_bytes(int n, int mixer, int state_dtype, size_t* bytes) {
+  if (!bytes) return fail(QAOA_ERR_INVALID, "bytes is NULL");
+  int rc = validate_xy(n, mixer, state_dtype);
+  if (rc) return rc;
+  *bytes = xy_work_bytes(n, mixer, state_dtype);
+  return QAOA_OK;
+}
+
+int qaoa_xy_plan_describe(int n, int mixer, int state_dtype, int* out, int cap) {
+  if (validate_xy(n, mixer, state_dtype)) return -QAOA_ERR_INVALID;
+  const XyPlan pl = make_xy_plan(n, mixer, state_elem_bytes(state_dtype));
+  std::vector<int> v{(int)pl.sweeps.size(), pl.eb, pl.single ? 1 : 0};
+  for (const auto& sw : pl.sweeps) {
+    v.insert(v.end(), {sw.g.tb, sw.g.R, sw.g.hA, sw.g.qA, sw.g.qB, (int)sw.gates.size()});
+    for (const auto& e : sw.gates) { v.push_back(e.first); v.push_back(e.second); }
+  }
+  if (out) for (int i = 0; i < (int)v.size() && i < cap; ++i) out[i] = v[i];
+  return (int)v.size();
+}
+
+int qaoa_evolve_xy(int n, int p, const double* gamma, const double* beta, int mixer, const void* d_diag,
+                   int diag_dtype, double diag_offset, size_t diag_bytes, void* d_state, int state_dtype,
+                   size_t state_bytes, int init, int k, double* d_out, void* d_work, size_t work_bytes,
+                   void* stream) {
+  int rc = validate_xy(n, mixer, state_dtype);
+  if (rc) return rc;
+  rc = validate_common(n, d_diag, diag_dtype, diag_offset, diag_bytes, d_state, state_dtype, state_bytes);
+  if (rc) return rc;
+  rc = validate_angles(p, gamma, beta);
+  if (rc) return rc;
+  if (init != QAOA_INIT_GIVEN && init != QAOA_INIT_PLUS && init != QAOA_INIT_DICKE)
+    return fail(QAOA_ERR_INVALID, "init must be QAOA_INIT_GIVEN, _PLUS or _DICKE");
+  if (init == QAOA_INIT_DICKE && (k < 0 || k > n)) return fail(QAOA_ERR_INVALID, "Dicke weight k=%d not in [0, n]", k);
+  const size_t need = xy_work_bytes(n, mixer, state_dtype);
+  if (!d_work || work_bytes < need) return fail(QAOA_ERR_NOMEM, "workspace too small: need %zu bytes", need);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const uint64_t N = (uint64_t)1 << n;
+  if (p == 0 && init == QAOA_INIT_GIVEN) {
+    if (d_out) return enqueue_expectation(n, d_state, state_dtype, d_diag, diag_dtype, diag_offset, d_out, d_work, st);
+    return QAOA_OK;
+  }
+  const XyPlan pl = make_xy_plan(n, mixer, state_elem_bytes(state_dtype));
+  for (const auto& sw : pl.sweeps)
+    if ((int)sw.gates.size() > qk::kMaxXyGates)
+      return fail(QAOA_ERR_UNSUPPORTED, "internal: %zu gates in one XY sweep (max %d)", sw.gates.size(), qk::kMaxXyGates);
+  uint64_t blocks_max = 1;
+  for (const auto& sw : pl.sweeps) blocks_max = std::max(blocks_max, plan_blocks(n, sw.g));
+  const size_t stride = 2 * std::max<uint64_t>(blocks_max, kExpectBlocks);
+  char* wk = reinterpret_cast<char*>(d_work);
+  double* partials = reinterpret_cast<double*>(wk);
+  double* pset = reinterpret_cast<double*>(wk + sizeof(double) * stride);
+  const size_t pset_bytes = ((qk::kParamRow * sizeof(double) * qk::kPrepRows + 255) / 256) * 256;
+  double2* tab = reinterpret_cast<double2*>(wk + sizeof(double) * stride + pset_bytes);
+  double* tmp = reinterpret_cast<double*>(wk + sizeof(double) * stride + pset_bytes +
+                                          qk::kPrepRows * qk::kTabRow * sizeof(double2));
+  const bool use_tab = diag_dtype != QAOA_DIAG_F64;
+
+  qk::XyArgs a{};
+  a.s.psi = d_state;
+  a.s.diag = d_diag;
+  a.s.diag_offset = diag_offset;
+  a.s.ptab = tab;
+  a.s.pset = pset;
+  a.s.partials = partials;
+  a.s.partials_stride = stride;
+  a.s.p_total = qk::kPrepRows;
+  a.s.set_stride_bytes = N * state_elem_bytes(state_dtype);
+  if (init == QAOA_INIT_DICKE) {
+    double cnk = 1.0;
+    for (int t = 1; t <= k; ++t) cnk = cnk * (double)(n - k + t) / (double)t;
+    a.s.amp0 = 1.0 / std::sqrt(cnk);
+    a.dicke_k = k;
+  } else {
+    a.s.amp0 = std::pow(2.0, -0.5 * n);
+    a.dicke_k = -1;
+  }
+  const bool gen = init != QAOA_INIT_GIVEN;
+  uint64_t last_blocks = 1;
+  auto set_gates = [&](const XySweep& sw, int count) {
+    a.ngates = count;
+    for (int e = 0; e < count; ++e) {
+      a.gate[e][0] = (int8_t)sw.gates[e].first;
+      a.gate[e][1] = (int8_t)sw.gates[e].second;
+    }
+  };
+  if (p == 0) {  // the initial state only (and its objective)
+    a.s.g = pl.sweeps[0].g;
+    a.s.nlayers = 0;
+    a.s.layer0 = 0;
+    set_gates(pl.sweeps[0], 0);
+    a.s.flags = qk::F_INIT | (d_out ? qk::F_EXPV : 0);
+    last_blocks = plan_blocks(n, a.s.g);
+    launch_xy(a, state_dtype, diag_dtype, pl.eb, last_blocks, 1, st);
+    LAUNCH_CHECK("qaoa_xy_kernel");
+  }
+  for (int l0 = 0; l0 < p; l0 += qk::kMaxLayersPerLaunch) {
+    const int nl = std::min(qk::kMaxLayersPerLaunch, p - l0);
+    qk::PrepArgs pa{};
+    pa.pset = pset;
+    pa.tab = use_tab ? tab : nullptr;
+    pa.base = use_tab ? table_base(diag_dtype, diag_offset) : 0.0;
+    pa.off = diag_offset;
+    pa.rows = nl;
+    for (int i = 0; i < nl; ++i) { pa.gamma[i] = gamma[l0 + i]; pa.beta[i] = beta[l0 + i]; }
+    hipLaunchKernelGGL(qk::layer_prep_kernel, dim3(nl), dim3(256), 0, st, pa);
+    LAUNCH_CHECK("layer_prep_kernel");
+    if (pl.single) {
+      a.s.g = pl.sweeps[0].g;
+      a.s.nlayers = nl;
+      a.s.layer0 = 0;
+      set_gates(pl.sweeps[0], (int)pl.sweeps[0].gates.size());
+      a.s.flags = qk::F_PHASE | ((l0 == 0 && gen) ? qk::F_INIT : 0) | ((l0 + nl == p && d_out) ? qk::F_EXPV : 0);
+      launch_xy(a, state_dtype, diag_dtype, pl.eb, 1, 1, st);
+      LAUNCH_CHECK("qaoa_xy_kernel");
+      continue;
+    }
+    a.s.nlayers = 1;
+    for (int l = l0; l < l0 + nl; ++l) {
+      a.s.layer0 = l - l0;
+      for (size_t sw = 0; sw < pl.sweeps.size(); ++sw) {
+        a.s.g = pl.sweeps[sw].g;
+        set_gates(pl.sweeps[sw], (int)pl.sweeps[sw].gates.size());
+        const bool last = (l == p - 1) && (sw + 1 == pl.sweeps.size());
+        a.s.flags = (sw == 0 ? qk::F_PHASE : 0) | ((sw == 0 && l == 0 && gen) ? qk::F_INIT : 0) |
+                    ((last && d_out) ? qk::F_EXPV : 0);
+        last_blocks = plan_blocks(n, a.s.g);
+        launch_xy(a, state_dtype, diag_dtype, pl.eb, last_blocks, 1, st);
+        LAUNCH_CHECK("qaoa_xy_kernel");
+      }
+    }
+  }
+  if (d_out) return enqueue_reduce(partials, last_blocks, stride, 1, tmp, d_out, st);
+  (void)work_bytes;
+  return QAOA_OK;
 }
 
 int qaoa_grad_workspace_bytes(int n, int p, int state_dtype, int diag_dtype, size_t* bytes) {
