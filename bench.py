@@ -31,6 +31,10 @@ CONFIGS = {
     # vector exactly (int32 and float64 are available through --diag)
     "labs26": dict(make="C2A", diag="u16"),
     "labs31": dict(make="C2B", diag="u16"),
+    # the same LABS n=26 p=10 evaluation with the Hamming-weight-preserving XY
+    # mixers (ring / complete graph on the qubits) in place of the X mixer
+    "xy_ring26": dict(make="C2A", diag="u16", mixer="xy_ring"),
+    "xy_complete26": dict(make="C2A", diag="u16", mixer="xy_complete"),
 }
 
 
@@ -51,6 +55,22 @@ def _sweep_bytes(sched, n, state_bytes, diag_bytes):
         if flags & (_lib.F_PHASE | _lib.F_FUSE | _lib.F_EXPV):
             b += diag_bytes * N
         per_launch.append(b)
+    return per_launch
+
+
+def _xy_sweep_bytes(n, p, nsweeps, state_bytes, diag_bytes):
+    """Algorithmic HBM bytes per launch of an XY-mixer evaluation: p layers of
+    `nsweeps` launches; the first generates |+> and only writes the state, every
+    other reads and writes it; each layer's first launch applies the phase and
+    reads the cost vector, and so does the last launch, which reduces E."""
+    N = 1 << n
+    per_launch = []
+    for l in range(p):
+        for sw in range(nsweeps):
+            b = (1 if (l == 0 and sw == 0) else 2) * state_bytes * N
+            if sw == 0 or (l == p - 1 and sw == nsweeps - 1):
+                b += diag_bytes * N
+            per_launch.append(b)
     return per_launch
 
 
@@ -90,7 +110,7 @@ def measured_traffic(workload: str):
         return None
 
 
-def cpu_baseline(cfg, budget_s=12.0):
+def cpu_baseline(cfg, budget_s=12.0, mixer=None):
     """Time the FP64 oracle on whole QAOA layers of the same workload, repeating
     evaluations from |+> until about `budget_s` of work is done (at least one
     layer); scale to evaluations per second."""
@@ -98,6 +118,7 @@ def cpu_baseline(cfg, budget_s=12.0):
 
     import oracle
     n, p = cfg["n"], cfg["p"]
+    xy_kind = {None: None, "xy_ring": oracle.XY_RING, "xy_complete": oracle.XY_COMPLETE}[mixer]
     t0 = time.perf_counter()
     c = oracle.diag_labs(n).astype(np.float64)
     t_diag = time.perf_counter() - t0
@@ -110,7 +131,10 @@ def cpu_baseline(cfg, budget_s=12.0):
         if l == 0:
             psi = plus.copy()
         psi = oracle.apply_phase(n, c, cfg["gamma"][l], psi)
-        psi = oracle.apply_mixer(n, cfg["beta"][l], psi)
+        if xy_kind is None:
+            psi = oracle.apply_mixer(n, cfg["beta"][l], psi)
+        else:
+            psi = oracle.apply_xy_mixer(n, xy_kind, cfg["beta"][l], psi)
         layers += 1
         if time.perf_counter() - t0 >= budget_s:
             break
@@ -118,7 +142,9 @@ def cpu_baseline(cfg, budget_s=12.0):
     evals_per_s = layers / (t_layers * p)
     return dict(value=evals_per_s, unit="evals/s", cores=oracle.num_threads(), kind="oracle",
                 sample=f"{layers} layers ({layers / p:.1f} evaluations of {p} layers) of the same workload "
-                       f"(n={n}, FP64 complex128 state, phase + {n} single-qubit mixer passes per layer) in "
+                       f"(n={n}, FP64 complex128 state, phase + "
+                       f"{'%d single-qubit' % n if xy_kind is None else len(oracle.xy_edges(n, xy_kind))} "
+                       f"{'mixer' if xy_kind is None else mixer + ' two-qubit'} passes per layer) in "
                        f"{t_layers:.2f} s, scaled to evaluations/s; cost vector built separately in "
                        f"{t_diag:.2f} s and excluded like the GPU precompute")
 
@@ -321,8 +347,18 @@ def main(argv=None):
     out = torch.empty(2, dtype=torch.float64, device=dev)
     work = _lib.alloc_workspace(_lib.QAOA_OP_EVOLVE, n, _lib.state_dtype_code(psi), _lib.diag_dtype_code(diag), dev)
 
-    def step():
-        q.qaoa_evolve(n, gamma, beta, diag, psi, init=True, diag_offset=off, out=out, work=work)
+    mixer = spec.get("mixer")
+    if mixer:
+        mcode = _lib.MIXER_NAMES[mixer]
+        work = torch.empty(max(16, _lib.xy_workspace_bytes(n, mcode, _lib.state_dtype_code(psi))),
+                           dtype=torch.uint8, device=dev)
+
+        def step():
+            q.qaoa_evolve_xy(n, gamma, beta, diag, psi, mixer=mcode, init=_lib.INIT_PLUS, diag_offset=off, out=out,
+                             work=work)
+    else:
+        def step():
+            q.qaoa_evolve(n, gamma, beta, diag, psi, init=True, diag_offset=off, out=out, work=work)
 
     for _ in range(max(1, args.warmup)):  # at least one evaluation, the reference for reproducibility
         step()
@@ -345,9 +381,15 @@ def main(argv=None):
         print(f"bench.py: non-reproducible or non-finite objective {e_first} vs {e_last}", file=sys.stderr)
         return 1
 
-    plan = _lib.plan_describe(n, _lib.state_dtype_code(psi))
-    sched = _lib.schedule_describe(n, p, _lib.state_dtype_code(psi))
-    per_launch = _sweep_bytes(sched, n, S, D)
+    if mixer:
+        plan = _lib.xy_plan_describe(n, mcode, _lib.state_dtype_code(psi))
+        per_launch = _xy_sweep_bytes(n, p, len(plan["sweeps"]), S, D)
+        kernel = "qaoa_xy_kernel"
+    else:
+        plan = _lib.plan_describe(n, _lib.state_dtype_code(psi))
+        sched = _lib.schedule_describe(n, p, _lib.state_dtype_code(psi))
+        per_launch = _sweep_bytes(sched, n, S, D)
+        kernel = "qaoa_sweep_kernel"
     launches = len(per_launch)
     bytes_per_eval = float(sum(per_launch))
     # the timed region holds `launches` sweep launches and one tiny finalize
@@ -356,7 +398,8 @@ def main(argv=None):
     achieved = (bytes_per_eval / launches) / (avg_launch_ms * 1e-3) / 1e9
 
     res = {
-        "metric": METRIC if args.config == "labs26" else f"QAOA expectation evals/s, LABS n={n} p={p}",
+        "metric": METRIC if args.config == "labs26" else
+        f"QAOA expectation evals/s, LABS n={n} p={p}" + (f", {mixer} mixer" if mixer else ""),
         "value": args.steps / (ms_total * 1e-3),
         "unit": "evals/s",
         "n_gpus": 1,
@@ -369,22 +412,23 @@ def main(argv=None):
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": cfg["name"], "problem": "LABS", "n": n, "p": p, "state": cfg["dtype"],
+            "workload": cfg["name"] + (f"+{mixer}" if mixer else ""), "problem": "LABS", "n": n, "p": p,
+            "state": cfg["dtype"], "mixer": mixer or "x",
             "cost_vector": {"i32": "int32", "u16": "uint16", "f64": "float64"}[spec["diag"]],
             "schedule": "linear ramp, seeded", "sweeps_per_layer": len(plan["sweeps"]),
             "tile_bits": plan["sweeps"][0]["tb"], "wide_tiles": args.wide_tiles, "fuse_layers": args.fuse_layers,
-            "launches_per_eval": len(sched),
+            "launches_per_eval": launches,
             "precompute_ms": precompute_ms, "E": float(e_last[0]), "norm": float(e_last[1]),
             "wall_s_timed": wall,
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "qaoa_sweep_kernel",
+            "kernel": kernel,
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(cfg["name"]),
+            "traffic": measured_traffic(cfg["name"] + (f"_{mixer}" if mixer else "")),
             "bytes_per_launch": bytes_per_eval / launches,
             "launches_per_step": launches,
             "avg_launch_ms": avg_launch_ms,
@@ -393,7 +437,7 @@ def main(argv=None):
     if not args.no_cpu_baseline:
         del psi, diag, work
         torch.cuda.empty_cache()
-        res["cpu_baseline"] = cpu_baseline(cfg, args.cpu_budget)
+        res["cpu_baseline"] = cpu_baseline(cfg, args.cpu_budget, mixer)
     print(json.dumps(res), flush=True)
     return 0
 
