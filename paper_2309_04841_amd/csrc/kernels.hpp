@@ -133,7 +133,7 @@ struct DI32 {
     return u < 65536u ? (int32_t)u : -1;
   }
   static constexpr double kTableBase = -32768.0;
-  static constexpr int kTabLds = 512;  // LDS entries: HI|LO, F1|LO or F3|F2
+  static constexpr int kTabLds = 288;  // LDS entries: HI|MID|LO, F1|MID|LO or F3|F2M|F2L
   static constexpr bool kPack16 = false;
   using RawT = int32_t;
   __device__ static __forceinline__ double value(RawT r) { return (double)r; }
@@ -150,7 +150,7 @@ struct DU16 {
   }
   __device__ static __forceinline__ int32_t tab_index(int32_t v) { return v; }
   static constexpr double kTableBase = 0.0;
-  static constexpr int kTabLds = 512;
+  static constexpr int kTabLds = 288;
   static constexpr bool kPack16 = true;  // two stored values fit one 32-bit register
   using RawT = int32_t;
   __device__ static __forceinline__ double value(RawT r) { return (double)r; }
@@ -173,23 +173,28 @@ struct DF64 {
 
 // Phase tables for integer cost vectors.  With u = stored - base in [0, 2^16)
 // the cost is c = u + base + offset, and
-//   exp(-i g c) = HI[u >> 8] * LO[u & 255],
-//   HI[m] = exp(-i g (256 m + base + offset)),  LO[j] = exp(-i g j),
+//   exp(-i g c) = HI[u >> 8] * MID[(u >> 4) & 15] * LO[u & 15],
+//   HI[m] = exp(-i g (256 m + base + offset)),  MID[j] = exp(-i g 16 j),
+//   LO[j] = exp(-i g j),
 // each entry from one sincos of an exactly representable integer times g.
+// MID and LO are 16 entries of 16 bytes: each occupies every LDS bank exactly
+// once, so their gathers never conflict (a 256-entry low table did, at
+// random indices); HI sees few distinct indices for costs of small range.
 // int32 values outside that range use the bytes b0..b3 of the stored value v
-// (two's complement, b3 signed), in two passes of the same two-table product:
-//   exp(-i g (v + offset)) = (F1[b1] * LO[b0]) * (F3[b3] * F2[b2]),
-//   F1[m] = exp(-i g 256 m),  F2[m] = exp(-i g 65536 m),
+// (two's complement, b3 signed), in two passes of the same three-table product:
+//   exp(-i g (v + offset)) = (F1[b1] * MID[b0 >> 4] * LO[b0 & 15])
+//                          * (F3[b3] * F2M[b2 >> 4] * F2L[b2 & 15]),
+//   F1[m] = exp(-i g 256 m),  F2M[j] = exp(-i g 2^20 j),  F2L[j] = exp(-i g 2^16 j),
 //   F3[m] = exp(-i g (2^24 s(m) + offset)),  s(m) = m - 256 [m >= 128].
-// A layer's row holds HI, LO, F1, F2, F3 (256 double2 (cos, -sin) each).
-constexpr int kTabEntries = 512;  // HI then LO: the part staged for in-range values
-constexpr int kTabRow = 1280;     // row stride: HI, LO, F1, F2, F3
+// A layer's row holds HI, MID, LO, F1, F3, F2M, F2L (double2 (cos, -sin)).
+constexpr int kTabEntries = 288;  // HI, MID, LO: the part staged for in-range values
+constexpr int kTabRow = 832;      // row stride: HI 256, MID 16, LO 16, F1 256, F3 256, F2M 16, F2L 16
 constexpr int kParamRow = 4;      // doubles per parameter row: gamma, cos beta, sin beta, tan beta
 
 // Per-layer parameters, computed on the device for every path so that batched
 // and single evaluations use bit-identical values: row r gets
 // pset[4r..4r+3] = (gamma, cos beta, sin beta, tan beta) and, when tab != nullptr, the
-// phase tables tab[512 r ..].  Angles come from device arrays (gamma_d, beta_d)
+// phase tables tab[kTabRow r ..].  Angles come from device arrays (gamma_d, beta_d)
 // or, when those are null, from the kernel arguments (at most kPrepRows rows).
 struct PrepArgs {
   const double* gamma_d;
@@ -218,14 +223,20 @@ __global__ void __launch_bounds__(256) layer_prep_kernel(const PrepArgs a) {
   }
   if (a.tab != nullptr) {
     for (int e = threadIdx.x; e < kTabRow; e += blockDim.x) {
-      const int m = e & 255;
       double v;
-      switch (e >> 8) {
-        case 0: v = 256.0 * (double)m + a.base; break;                            // HI
-        case 1: v = (double)m; break;                                             // LO
-        case 2: v = 256.0 * (double)m; break;                                     // F1
-        case 3: v = 65536.0 * (double)m; break;                                   // F2
-        default: v = 16777216.0 * (double)(m < 128 ? m : m - 256) + a.off; break;  // F3
+      if (e < 256) {
+        v = 256.0 * (double)e + a.base;  // HI
+      } else if (e < 288) {
+        const int j = (e - 256) & 15;
+        v = e < 272 ? 16.0 * (double)j : (double)j;  // MID, LO
+      } else if (e < 544) {
+        v = 256.0 * (double)(e - 288);  // F1
+      } else if (e < 800) {
+        const int m = e - 544;
+        v = 16777216.0 * (double)(m < 128 ? m : m - 256) + a.off;  // F3
+      } else {
+        const int j = (e - 800) & 15;
+        v = e < 816 ? 1048576.0 * (double)j : 65536.0 * (double)j;  // F2M, F2L
       }
       double sn, cs;
       sincos(g * v, &sn, &cs);
@@ -415,24 +426,31 @@ __device__ __forceinline__ void cmul_inplace(double& r, double& i, double fr, do
 }
 
 // Table passes of the integer phase.  Every pass multiplies each element by
-// T[(x >> 8) & 255] * T[256 + (x & 255)] with x = (v + add) >> shift, where v is
-// the stored value and T the 512 entries staged in LDS:
-//   in range (one pass):  T = HI|LO, add = -base, shift 0;
-//   out of range (int32): T = F1|LO, then T = F3|F2 with shift 16 (the byte
-//   decomposition).
+// T[(x >> 8) & 255] * T[256 + ((x >> 4) & 15)] * T[272 + (x & 15)] with
+// x = (v + add) >> shift, where v is the stored value and T the 288 entries
+// staged in LDS:
+//   in range (one pass):  T = HI|MID|LO, add = -base, shift 0;
+//   out of range (int32): T = F1|MID|LO, then T = F3|F2M|F2L with shift 16 (the
+//   byte decomposition).
 // One code path serves both cases, so the rare case costs no registers in the
-// common one.  Returns the number of passes; prepare_pass stages pass `pass`.
+// common one; prepare_pass stages pass `pass`.
 __device__ __forceinline__ void prepare_pass(double2* tab, const double2* row, uint32_t tid, int pass) {
   __syncthreads();  // readers of the previous tables are done
-  for (uint32_t e = tid; e < 256u; e += blockDim.x) {
+  for (uint32_t e = tid; e < 288u; e += blockDim.x) {
     if (pass == 0) {
-      tab[e] = row[512 + e];  // F1 (LO stays)
+      if (e < 256u) tab[e] = row[288 + e];  // F1 (MID, LO stay)
     } else {
-      tab[e] = row[1024 + e];       // F3
-      tab[256 + e] = row[768 + e];  // F2
+      tab[e] = row[544 + e];  // F3, F2M, F2L
     }
   }
   __syncthreads();
+}
+
+// The phase factor of table index x (both cases above).
+__device__ __forceinline__ double2 table_phase(const double2* tab, uint32_t x) {
+  const double2 h = tab[(x >> 8) & 255u], m = tab[256u + ((x >> 4) & 15u)], l = tab[272u + (x & 15u)];
+  const double2 hm = make_double2(fma(h.x, m.x, -h.y * m.y), fma(h.x, m.y, h.y * m.x));
+  return make_double2(fma(hm.x, l.x, -hm.y * l.y), fma(hm.x, l.y, hm.y * l.x));
 }
 
 // Stage HI|LO and decide (workgroup-uniform) whether every value of the tile is
@@ -491,9 +509,8 @@ __device__ __forceinline__ void phase_from_raw(double (&vr)[1 << EB], double (&v
       for (int k0 = 0; k0 < E; k0 += 4) {
 #pragma unroll
         for (int k = k0; k < k0 + 4 && k < E; ++k) {
-          const uint32_t x = ((uint32_t)cv[k] + add) >> shift;
-          const double2 h = tab[(x >> 8) & 255u], lo = tab[256 + (x & 255u)];
-          cmul_inplace(vr[k], vi[k], fma(h.x, lo.x, -h.y * lo.y), fma(h.x, lo.y, h.y * lo.x));
+          const double2 f = table_phase(tab, ((uint32_t)cv[k] + add) >> shift);
+          cmul_inplace(vr[k], vi[k], f.x, f.y);
         }
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -819,11 +836,9 @@ __device__ __forceinline__ void undo_phase(double (&vr)[1 << EB], double (&vi)[1
       for (int k0 = 0; k0 < E; k0 += 4) {
 #pragma unroll
         for (int k = k0; k < k0 + 4 && k < E; ++k) {
-          const uint32_t x = ((uint32_t)cv[k] + add) >> shift;
-          const double2 h = tab[(x >> 8) & 255u], lo = tab[256 + (x & 255u)];
-          const double fr = fma(h.x, lo.x, -h.y * lo.y), fi = -fma(h.x, lo.y, h.y * lo.x);  // conjugate
-          cmul_inplace(vr[k], vi[k], fr, fi);
-          cmul_inplace(lr[k], li[k], fr, fi);
+          const double2 f = table_phase(tab, ((uint32_t)cv[k] + add) >> shift);
+          cmul_inplace(vr[k], vi[k], f.x, -f.y);  // conjugate
+          cmul_inplace(lr[k], li[k], f.x, -f.y);
         }
         __builtin_amdgcn_sched_barrier(0);
       }

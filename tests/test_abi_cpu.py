@@ -41,9 +41,9 @@ def test_version_and_last_error():
 
 def test_workspace_bytes():
     # per-block (E, norm) partials of the last sweep + parameter rows (4 doubles, 256-byte aligned) and
-    # phase tables (5 x 256 entries) of 33 layers (a chunk of 32 and the next one) + the
+    # phase tables (3 x 256 + 4 x 16 entries) of 33 layers (a chunk of 32 and the next one) + the
     # first stage of the two-stage reduction
-    assert _lib.workspace_bytes(_lib.QAOA_OP_EVOLVE, 26, _lib.QAOA_C128) == 16 * (1 << 12) + 1280 + 33 * 1280 * 16 + 16 * 1024
+    assert _lib.workspace_bytes(_lib.QAOA_OP_EVOLVE, 26, _lib.QAOA_C128) == 16 * (1 << 12) + 1280 + 33 * 832 * 16 + 16 * 1024
     assert _lib.workspace_bytes(_lib.QAOA_OP_PRECOMPUTE, 20, diag_dtype=_lib.QAOA_DIAG_F64) == 0
     assert _lib.workspace_bytes(_lib.QAOA_OP_PRECOMPUTE, 20, diag_dtype=_lib.QAOA_DIAG_U16) >= 4 << 20
     with pytest.raises(_lib.QaoaError):

@@ -125,7 +125,7 @@ def test_xy_workspace_bytes():
         for mixer in (_lib.MIXER_XY_RING, _lib.MIXER_XY_COMPLETE):
             nb = _lib.xy_workspace_bytes(n, mixer, _lib.QAOA_C128)
             blocks = max(1, (1 << n) >> 12)
-            assert nb >= 16 * blocks + 33 * 1280 * 16
+            assert nb >= 16 * blocks + 33 * 832 * 16
     for bad in ((1, 1), (31, 1), (10, 0), (10, 3)):
         with pytest.raises(_lib.QaoaError):
             _lib.xy_workspace_bytes(bad[0], bad[1], _lib.QAOA_C128)
