@@ -373,13 +373,18 @@ __device__ __forceinline__ void exchange_sync(bool local) {
   }
 }
 
+// Per-thread part of the swizzled LDS byte address in window w.
 template <class S, int EB>
-__device__ __forceinline__ void exchange_c(double (&vr)[1 << EB], double (&vi)[1 << EB], typename S::L* lds,
-                                           const TileGeom& g, uint32_t tid, int wf, int wt) {
-  // linear swizzle in bytes: per-thread part here, per-register part (g.loff,
-  // already in bytes) from the host, so each access costs one XOR
-  const uint32_t pf = swz<S::kLdsBytes>(thr_part<EB>(tid, wf)) * S::kLdsBytes;
-  const uint32_t pt = swz<S::kLdsBytes>(thr_part<EB>(tid, wt)) * S::kLdsBytes;
+__device__ __forceinline__ uint32_t lds_tpart(uint32_t tid, int w) {
+  return swz<S::kLdsBytes>(thr_part<EB>(tid, w)) * S::kLdsBytes;
+}
+
+// Window change wf -> wt through LDS.  Linear swizzle in bytes: per-thread
+// parts pf, pt (lds_tpart of the two windows), per-register part (g.loff,
+// already in bytes) from the host, so each access costs one XOR.
+template <class S, int EB>
+__device__ __forceinline__ void exchange_p(double (&vr)[1 << EB], double (&vi)[1 << EB], typename S::L* lds,
+                                           const TileGeom& g, int wf, int wt, uint32_t pf, uint32_t pt) {
   // a wave-local change writes and reads only the wave's own positions; the
   // positions it writes were last read by the same wave, so no barrier is
   // needed after the reads either
@@ -407,6 +412,12 @@ __device__ __forceinline__ void exchange_c(double (&vr)[1 << EB], double (&vi)[1
     for (int k = 0; k < (1 << EB); ++k) S::lget(lds, pt ^ g.loff[wt][k], vr[k], vi[k]);
     if (!local) __syncthreads();
   }
+}
+
+template <class S, int EB>
+__device__ __forceinline__ void exchange_c(double (&vr)[1 << EB], double (&vi)[1 << EB], typename S::L* lds,
+                                           const TileGeom& g, uint32_t tid, int wf, int wt) {
+  exchange_p<S, EB>(vr, vi, lds, g, wf, wt, lds_tpart<S, EB>(tid, wf), lds_tpart<S, EB>(tid, wt));
 }
 
 // exp(-i g c) evaluated directly from the double-precision angle g * c.  Kept
@@ -542,16 +553,20 @@ __device__ __forceinline__ void load_cost(typename D::RawT (&cv)[1 << EB], const
 // chunk order or (REV) in reverse chunk order; the gates commute, so both
 // orders give the same layer.  Each gate is applied divided by cos(beta)
 // (rx_pair_t with tn = tan beta): the caller multiplies the tile by
-// cos(beta)^(tb - act_lo).  Returns the final window.
+// cos(beta)^(tb - act_lo).  Returns the final window; pcur holds lds_tpart of
+// the current window on entry and on return (each change computes only the
+// new window's part).
 template <class S, int EB, bool REV = false>
 __device__ __forceinline__ int apply_mixer(double (&vr)[1 << EB], double (&vi)[1 << EB], typename S::L* lds,
-                                           const TileGeom& g, uint32_t tid, int w, double tn) {
+                                           const TileGeom& g, uint32_t tid, int w, double tn, uint32_t& pcur) {
   constexpr int E = 1 << EB;
   for (int i = 0; i < g.nchunks; ++i) {
     const Chunk ch = g.chunk[REV ? g.nchunks - 1 - i : i];
     if (ch.w != w) {
-      exchange_c<S, EB>(vr, vi, lds, g, tid, w, ch.w);
+      const uint32_t pt = lds_tpart<S, EB>(tid, ch.w);
+      exchange_p<S, EB>(vr, vi, lds, g, w, ch.w, pcur, pt);
       w = ch.w;
+      pcur = pt;
     }
     // every register bit takes a butterfly; bits outside [jlo, jhi) take the
     // identity (t = 0 gives exactly (y0, y1)).  Straight-line code: a branch
@@ -657,7 +672,8 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
     phase_from_raw<S, D, EB>(vr, vi, pc, a, lp, tid, tab);
   }
   const int nq = a.g.tb - a.g.act_lo;  // gates per layer in this tile
-  w = apply_mixer<S, EB>(vr, vi, lds, a.g, tid, w, lp.tn);
+  uint32_t pcur = lds_tpart<S, EB>(tid, w);
+  w = apply_mixer<S, EB>(vr, vi, lds, a.g, tid, w, lp.tn, pcur);
   scale_tile(vr, vi, ipow(lp.ca, nq));
   if constexpr (FUSE) {
     const LayerParams lq = layer_params(a, set, 1);
@@ -668,14 +684,14 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
       load_cost<D, EB>(cv, a, base, tid, w);
     }
     phase_from_raw<S, D, EB, D::kTable>(vr, vi, cv, a, lq, tid, tab);
-    w = apply_mixer<S, EB, true>(vr, vi, lds, a.g, tid, w, lq.tn);  // ends in the load mapping
+    w = apply_mixer<S, EB, true>(vr, vi, lds, a.g, tid, w, lq.tn, pcur);  // ends in the load mapping
     scale_tile(vr, vi, ipow(lq.ca, nq));
   }
 
   double e_part = 0.0, n_part = 0.0;
   const int w_out = EXPV ? w_load : (FUSE ? w : a.g.w_store);
   if (w != w_out) {
-    exchange_c<S, EB>(vr, vi, lds, a.g, tid, w, w_out);
+    exchange_p<S, EB>(vr, vi, lds, a.g, w, w_out, pcur, lds_tpart<S, EB>(tid, w_out));
     w = w_out;
   }
   if constexpr (EXPV) {
@@ -730,8 +746,9 @@ __global__ void __launch_bounds__(512) qaoa_tile_kernel(const SweepArgs a) {
     load_cost<D, EB>(pc, a, 0, tid, w);
     phase_from_raw<S, D, EB>(vr, vi, pc, a, lp, tid, tab);
     // alternate the chunk order: each layer starts in the window the last one ended in
-    if (l & 1) w = apply_mixer<S, EB, true>(vr, vi, lds, a.g, tid, w, lp.tn);
-    else w = apply_mixer<S, EB>(vr, vi, lds, a.g, tid, w, lp.tn);
+    uint32_t pcur = lds_tpart<S, EB>(tid, w);
+    if (l & 1) w = apply_mixer<S, EB, true>(vr, vi, lds, a.g, tid, w, lp.tn, pcur);
+    else w = apply_mixer<S, EB>(vr, vi, lds, a.g, tid, w, lp.tn, pcur);
     scale_tile(vr, vi, ipow(lp.ca, a.g.tb));
   }
   double e_part = 0.0, n_part = 0.0;
