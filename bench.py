@@ -205,6 +205,105 @@ def bench_batch(args):
             "effective_GBps": bytes_per_set * batch / t_batch / 1e9}
 
 
+def _adjoint_bytes(sched, n, state_bytes, diag_bytes):
+    """Algorithmic HBM bytes per reverse-pass launch of the gradient: every
+    launch reads and writes psi and lambda, except the first, which reads psi
+    and the cost vector and writes both (lambda = c psi); launches that undo a
+    phase (A_PHASE, or A_FUSE joining two layers) read the cost vector."""
+    from paper_2309_04841_amd import _lib
+    N = 1 << n
+    out = []
+    for _sw, _layer, flags in sched:
+        if flags & _lib.A_FIRST:
+            b = 3 * state_bytes * N + diag_bytes * N
+        else:
+            b = 4 * state_bytes * N
+            if flags & (_lib.A_PHASE | _lib.A_FUSE):
+                b += diag_bytes * N
+        out.append(b)
+    return out
+
+
+def bench_grad(args):
+    """Adjoint gradient (E, dE/dgamma, dE/dbeta): LABS n=24, p=20, complex128,
+    uint16 cost vector.  One step = one qaoa_grad call (forward evaluation +
+    reverse pass); the reverse pass's time is the gradient's time minus that of
+    the same forward evaluation timed alone."""
+    import numpy as np
+    import torch
+
+    import paper_2309_04841_amd as q
+    from paper_2309_04841_amd import _lib
+    import workloads as W
+    cfg = W.C4()
+    n, p = cfg["n"], cfg["p"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    gamma, beta = np.asarray(cfg["gamma"]), np.asarray(cfg["beta"])
+    diag, off = q.qaoa_precompute_diag(n, cfg["terms"], "u16", device=dev)
+    psi = torch.empty(1 << n, dtype=torch.complex128, device=dev)
+    adj = torch.empty_like(psi)
+    out = torch.empty(1 + 2 * p, dtype=torch.float64, device=dev)
+    eo = torch.empty(2, dtype=torch.float64, device=dev)
+    gw = torch.empty(_lib.grad_workspace_bytes(n, p, _lib.QAOA_C128, _lib.QAOA_DIAG_U16), dtype=torch.uint8, device=dev)
+    ew = _lib.alloc_workspace(_lib.QAOA_OP_EVOLVE, n, _lib.QAOA_C128, _lib.QAOA_DIAG_U16, dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def grad():
+        q.qaoa_grad(n, gamma, beta, diag, psi, adj, diag_offset=off, out=out, work=gw)
+
+    def fwd():
+        q.qaoa_evolve(n, gamma, beta, diag, psi, init=True, diag_offset=off, out=eo, work=ew)
+
+    def timed(fn, k):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s.record(stream)
+        for _ in range(k):
+            fn()
+        e.record(stream)
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / k
+
+    ms_grad = timed(grad, args.steps)
+    g_first = out.cpu().numpy().copy()
+    ms_fwd = timed(fwd, args.steps)
+    grad()
+    torch.cuda.synchronize()
+    if not np.array_equal(g_first, out.cpu().numpy()) or not np.isfinite(g_first).all():
+        raise RuntimeError("non-reproducible or non-finite gradient")
+    sched = _lib.schedule_describe(n, p, _lib.QAOA_C128, kind=_lib.SCHED_ADJOINT)
+    per = _adjoint_bytes(sched, n, 16, 2)
+    ms_rev = ms_grad - ms_fwd
+    achieved = (sum(per) / len(per)) / (ms_rev / len(per) * 1e-3) / 1e9
+    res = {
+        "metric": f"QAOA gradient evals/s (adjoint), LABS n={n} p={p}",
+        "value": 1e3 / ms_grad, "unit": "gradients/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": max(1, args.warmup), "ms_per_step": ms_grad, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": cfg["name"], "problem": "LABS", "n": n, "p": p, "state": "complex128",
+                   "cost_vector": "uint16", "schedule": "linear ramp + N(0, 0.05), seeded",
+                   "forward_ms": ms_fwd, "reverse_ms": ms_rev, "reverse_launches": len(per),
+                   "E": float(g_first[0])},
+        "roofline": {"bound": "hbm", "kernel": "qaoa_adjoint_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": sum(per) / len(per), "launches_per_step": len(per),
+                     "avg_launch_ms": ms_rev / len(per)},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        c = oracle.diag_labs(n).astype(np.float64)
+        t0 = time.perf_counter()
+        oracle.grad(n, c, gamma, beta)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = dict(value=1.0 / dt, unit="gradients/s", cores=oracle.num_threads(), kind="oracle",
+                                   sample=f"one full gradient of the same workload (forward + adjoint, FP64) in "
+                                          f"{dt:.2f} s")
+    return res
+
+
 def bench_serve(args):
     """Served mix: Poisson arrivals at --rate, 60% objective / 40% gradient,
     LABS or 3-regular (odd n: 4-regular) MaxCut with n ~ U{16..30}, p ~ U{1..20}, complex64;
@@ -273,7 +372,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", choices=sorted(CONFIGS) + ["batch", "serve"], default="labs26")
+    ap.add_argument("--config", choices=sorted(CONFIGS) + ["batch", "serve", "grad"], default="labs26")
     ap.add_argument("--sets-per-pass", type=int, default=0, help="batch: states advanced together (0 = autotune)")
     ap.add_argument("--requests", type=int, default=120, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=40.0, help="serve: Poisson arrival rate (requests/s)")
@@ -300,9 +399,9 @@ def main(argv=None):
         print(json.dumps({"copy_calibration": {"bytes_read": nbytes, "bytes_written": nbytes, "dispatches": 3}}))
         return 0
 
-    if args.config in ("batch", "serve") and args.gpus == 1:
+    if args.config in ("batch", "serve", "grad") and args.gpus == 1:
         import torch  # noqa: F401
-        res = bench_batch(args) if args.config == "batch" else bench_serve(args)
+        res = {"batch": bench_batch, "serve": bench_serve, "grad": bench_grad}[args.config](args)
         print(json.dumps(res), flush=True)
         return 0
 
