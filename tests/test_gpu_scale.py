@@ -133,3 +133,36 @@ def test_n31_c64_properties(q):
     assert abs(e1[0] - e128[0]) <= 1e-5 * e128[0]
     del psi128, diag
     torch.cuda.empty_cache()
+
+
+def test_n33_c64_beyond_32bit_indices(q):
+    """2^33 elements (64 GiB complex64 state): every index computation above
+    2^32.  Cost values at sampled high indices against the oracle; beta=0 gives
+    E = n(n-1)/2 exactly in exact arithmetic; gamma=0 gives the same amplitude
+    exp(-i n sum beta) 2^{-n/2} at every index, checked at sampled high ones."""
+    n = 33
+    _say("precompute LABS n=33 u16")
+    diag, off = q.qaoa_precompute_diag(n, W.labs_terms(n), "u16", device="cuda")
+    rng = np.random.default_rng(33)
+    xs = np.concatenate([[0, (1 << 32) - 1, 1 << 32, (1 << n) - 1],
+                         rng.integers(1 << 32, 1 << n, size=2048), rng.integers(0, 1 << 32, size=1024)])
+    idx = torch.from_numpy(xs).cuda()
+    raw = diag.view(torch.int16)[idx].cpu().numpy().astype(np.int64) & 0xFFFF
+    assert np.array_equal(raw + int(off), oracle.diag_labs_at(n, xs))
+    psi = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    g, b = np.array([0.21, 0.33]), np.array([0.61, 0.17])
+    _say("n=33 c64 p=2 beta=0")
+    e0 = _E(q, n, diag, off, g, np.zeros(2), psi, out)
+    assert abs(e0[0] - n * (n - 1) / 2) <= 1e-5 * e0[0] and abs(e0[1] - 1.0) <= 1e-5
+    _say("n=33 c64 p=2 gamma=0")
+    _E(q, n, diag, off, np.zeros(2), b, psi, out)
+    ref = np.exp(-1j * n * b.sum()) * 2.0 ** (-n / 2)
+    got = psi[idx].cpu().numpy().astype(np.complex128)
+    assert np.max(np.abs(got - ref)) <= 1e-5 * abs(ref)
+    _say("n=33 c64 p=2")
+    e1 = _E(q, n, diag, off, g, b, psi, out)
+    assert abs(e1[1] - 1.0) <= 1e-5
+    assert 0.0 <= e1[0] <= sum((n - k) ** 2 for k in range(1, n))
+    del psi, diag
+    torch.cuda.empty_cache()
