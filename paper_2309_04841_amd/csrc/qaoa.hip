@@ -8,8 +8,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <set>
 #include <string>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -297,14 +300,32 @@ std::vector<std::pair<int, int>> bit_runs(const std::vector<int>& bits) {
   return r;
 }
 
-// Tile bits of a qubit set: the set plus [0, pmin); fits if at most tbmax bits
-// forming the run from 0 and at most two more runs.
-bool xy_fits(const std::set<int>& q, int pmin, int tbmax) {
-  std::set<int> b(q);
-  for (int i = 0; i < pmin; ++i) b.insert(i);
-  if ((int)b.size() > tbmax) return false;
-  const auto r = bit_runs(std::vector<int>(b.begin(), b.end()));
-  return (int)r.size() - (r.front().first == 0 ? 1 : 0) <= 2;
+// Tile bits of a qubit set (bit mask q): the set plus [0, pmin); fits if at
+// most tbmax bits forming the run from 0 and at most two more runs.
+bool xy_fits(uint64_t q, int pmin, int tbmax) {
+  const uint64_t b = q | ((1ull << pmin) - 1ull);
+  if (__builtin_popcountll(b) > tbmax) return false;
+  const int runs = __builtin_popcountll(b & ~(b << 1));
+  return runs - (int)(b & 1ull) <= 2;
+}
+
+// One pass over the pending gates in order with qubit set q: a gate is taken
+// when both qubits are in q and neither is blocked; any other gate blocks its
+// qubits (every later gate on them must follow it).  Returns the count taken
+// and, if `taken` is given, their indices in order.
+int xy_pass(const std::vector<std::pair<int, int>>& pend, uint64_t q, std::vector<size_t>* taken) {
+  uint64_t blocked = 0;
+  int cnt = 0;
+  for (size_t e = 0; e < pend.size(); ++e) {
+    const uint64_t m = (1ull << pend[e].first) | (1ull << pend[e].second);
+    if (!(blocked & m) && (q & m) == m) {
+      ++cnt;
+      if (taken) taken->push_back(e);
+    } else {
+      blocked |= m;
+    }
+  }
+  return cnt;
 }
 
 XySweep xy_sweep(int n, const std::set<int>& q, const std::vector<std::pair<int, int>>& edges, int pmin, int tbmax) {
@@ -331,7 +352,7 @@ XySweep xy_sweep(int n, const std::set<int>& q, const std::vector<std::pair<int,
   return sw;
 }
 
-XyPlan make_xy_plan(int n, int mixer, size_t elem_bytes) {
+XyPlan build_xy_plan(int n, int mixer, size_t elem_bytes) {
   XyPlan pl;
   const auto edges = xy_edges(n, mixer);
   if (n <= kXyTileBits) {
@@ -346,39 +367,62 @@ XyPlan make_xy_plan(int n, int mixer, size_t elem_bytes) {
   pl.eb = kEB;
   const int pmin = min_passenger_bits(elem_bytes);
   // Gates on disjoint qubits commute, so a sweep may take any gate whose
-  // earlier neighbours (earlier gates sharing a qubit) are all applied.  One
-  // pass in the fixed order per sweep: a gate whose qubits fit the tile and
-  // are not blocked is applied; otherwise its qubits become blocked, since
-  // every later gate on them must follow it.  The first pending gate is
-  // always applied, so every sweep makes progress.
-  std::vector<char> done(edges.size(), 0);
-  size_t remaining = edges.size();
-  while (remaining > 0) {
-    std::set<int> q;
-    std::vector<char> blocked(n, 0);
-    std::vector<std::pair<int, int>> run;
-    for (size_t e = 0; e < edges.size(); ++e) {
-      if (done[e]) continue;
-      const int i = edges[e].first, j = edges[e].second;
-      bool ok = !blocked[i] && !blocked[j];
-      if (ok) {
-        std::set<int> q2(q);
-        q2.insert(i);
-        q2.insert(j);
-        ok = xy_fits(q2, pmin, kXyTileBits);
-        if (ok) q.swap(q2);
+  // earlier neighbours (earlier gates sharing a qubit) are all applied: the
+  // gates one xy_pass takes.  Each sweep grows its qubit set from the
+  // passengers, adding the qubit (or, when no single qubit helps, the pair of
+  // one of the first pending gates) that lets the pass take the most gates,
+  // while the set fits a tile.  The first pending gate always fits with the
+  // passengers, so every sweep makes progress.
+  std::vector<std::pair<int, int>> pend = edges;
+  while (!pend.empty()) {
+    uint64_t q = (1ull << pmin) - 1ull;
+    for (;;) {
+      int best = xy_pass(pend, q, nullptr);
+      uint64_t add = 0, cand = 0;
+      for (const auto& e : pend) cand |= (1ull << e.first) | (1ull << e.second);
+      cand &= ~q;
+      for (int c = 0; c < n; ++c) {
+        if (!((cand >> c) & 1ull) || !xy_fits(q | (1ull << c), pmin, kXyTileBits)) continue;
+        const int cnt = xy_pass(pend, q | (1ull << c), nullptr);
+        if (cnt > best) { best = cnt; add = 1ull << c; }
       }
-      if (ok) {
-        done[e] = 1;
-        --remaining;
-        run.push_back(edges[e]);
-      } else {
-        blocked[i] = blocked[j] = 1;
+      if (!add) {
+        for (size_t e = 0; e < pend.size() && e < 40; ++e) {
+          const uint64_t m = (1ull << pend[e].first) | (1ull << pend[e].second);
+          if ((q | m) == q || !xy_fits(q | m, pmin, kXyTileBits)) continue;
+          const int cnt = xy_pass(pend, q | m, nullptr);
+          if (cnt > best) { best = cnt; add = m & ~q; }
+        }
       }
+      if (!add) break;
+      q |= add;
     }
-    pl.sweeps.push_back(xy_sweep(n, q, run, pmin, kXyTileBits));
+    std::vector<size_t> taken;
+    xy_pass(pend, q, &taken);
+    std::vector<std::pair<int, int>> run;
+    std::vector<char> used(pend.size(), 0);
+    for (size_t e : taken) { run.push_back(pend[e]); used[e] = 1; }
+    std::vector<std::pair<int, int>> rest;
+    for (size_t e = 0; e < pend.size(); ++e)
+      if (!used[e]) rest.push_back(pend[e]);
+    pend.swap(rest);
+    std::set<int> qs;
+    for (int b = 0; b < n; ++b)
+      if ((q >> b) & 1ull) qs.insert(b);
+    pl.sweeps.push_back(xy_sweep(n, qs, run, pmin, kXyTileBits));
   }
   return pl;
+}
+
+// Plans are built once per (n, mixer, element size) and kept for the process.
+XyPlan make_xy_plan(int n, int mixer, size_t elem_bytes) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, size_t>, XyPlan> cache;
+  const auto key = std::make_tuple(n, mixer, elem_bytes);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(key);
+  if (it == cache.end()) it = cache.emplace(key, build_xy_plan(n, mixer, elem_bytes)).first;
+  return it->second;
 }
 
 // ---------------------------------------------------------------------------
