@@ -195,14 +195,21 @@ def bench_batch(args):
         q.qaoa_evolve(n, gam[s], bet[s], diag, psi, diag_offset=off, out=o1, work=w1)
     torch.cuda.synchronize()
     t_single = time.perf_counter() - t0
-    bytes_per_set = sum(_sweep_bytes(_lib.schedule_describe(n, p, _lib.QAOA_C64), n, 8, 4))
+    per_launch = _sweep_bytes(_lib.schedule_describe(n, p, _lib.QAOA_C64), n, 8, 4)  # one state
+    groups = -(-batch // spp)
+    launches = len(per_launch) * groups  # each launch advances one group of spp states
+    achieved = sum(per_launch) * batch / t_batch / 1e9
     return {"metric": "batched QAOA evals/s, weighted MaxCut G(22,0.3) p=6, 512 sets", "value": batch / t_batch,
             "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-            "ms_per_step": 1e3 * t_batch, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "ms_per_step": 1e3 * t_batch, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
             "config": {"workload": cfg["name"], "n": n, "p": p, "sets": batch, "state": "complex64",
-                       "sets_per_pass": spp},
+                       "cost_vector": "int32", "sets_per_pass": spp},
             "single_path_evals_per_s": batch / t_single, "speedup_vs_single": t_single / t_batch,
-            "effective_GBps": bytes_per_set * batch / t_batch / 1e9}
+            "roofline": {"bound": "hbm", "kernel": "qaoa_sweep_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "bytes_per_launch": sum(per_launch) * batch / launches, "launches_per_step": launches,
+                         "avg_launch_ms": 1e3 * t_batch / launches}}
 
 
 def _adjoint_bytes(sched, n, state_bytes, diag_bytes):
@@ -288,7 +295,7 @@ def bench_grad(args):
                    "forward_ms": ms_fwd, "reverse_ms": ms_rev, "reverse_launches": len(per),
                    "E": float(g_first[0])},
         "roofline": {"bound": "hbm", "kernel": "qaoa_adjoint_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(cfg["name"]),
                      "bytes_per_launch": sum(per) / len(per), "launches_per_step": len(per),
                      "avg_launch_ms": ms_rev / len(per)},
     }
