@@ -549,6 +549,18 @@ __device__ __forceinline__ void load_cost(typename D::RawT (&cv)[1 << EB], const
   load_cost_g<D, EB>(cv, a.diag, base, tid, w, a.g);
 }
 
+// Tangent-form butterflies on register bits [LO, HI) of the window.
+template <int EB, int LO, int HI>
+__device__ __forceinline__ void butterflies(double (&vr)[1 << EB], double (&vi)[1 << EB], double t) {
+#pragma unroll
+  for (int j = LO; j < HI && j < EB; ++j) {
+#pragma unroll
+    for (int k = 0; k < (1 << EB); ++k) {
+      if (!(k & (1 << j))) rx_pair_t(vr[k], vi[k], vr[k | (1 << j)], vi[k | (1 << j)], t);
+    }
+  }
+}
+
 // Mixer gates of one layer on the tile's active qubits, window by window, in
 // chunk order or (REV) in reverse chunk order; the gates commute, so both
 // orders give the same layer.  Each gate is applied divided by cos(beta)
@@ -556,21 +568,34 @@ __device__ __forceinline__ void load_cost(typename D::RawT (&cv)[1 << EB], const
 // cos(beta)^(tb - act_lo).  Returns the final window; pcur holds lds_tpart of
 // the current window on entry and on return (each change computes only the
 // new window's part).
-template <class S, int EB, bool REV = false>
+//
+// Every register bit of a chunk takes a butterfly; bits outside [jlo, jhi)
+// take the identity (t = 0 gives exactly (y0, y1)).  Straight-line code: a
+// branch per bit made the compiler copy all 16 elements after each butterfly.
+// When PHI > PLO the caller guarantees that the last chunk (in plan order) has
+// jlo = PLO, jhi = PHI; that chunk is then applied outside the loop with only
+// its own butterflies (plans end with a chunk of one or two bits).
+template <class S, int EB, bool REV = false, int PLO = 0, int PHI = 0>
 __device__ __forceinline__ int apply_mixer(double (&vr)[1 << EB], double (&vi)[1 << EB], typename S::L* lds,
                                            const TileGeom& g, uint32_t tid, int w, double tn, uint32_t& pcur) {
   constexpr int E = 1 << EB;
-  for (int i = 0; i < g.nchunks; ++i) {
-    const Chunk ch = g.chunk[REV ? g.nchunks - 1 - i : i];
-    if (ch.w != w) {
-      const uint32_t pt = lds_tpart<S, EB>(tid, ch.w);
-      exchange_p<S, EB>(vr, vi, lds, g, w, ch.w, pcur, pt);
-      w = ch.w;
+  constexpr bool kPart = PHI > PLO;
+  const int nloop = kPart ? g.nchunks - 1 : g.nchunks;
+  auto to_window = [&](int wt) {
+    if (wt != w) {
+      const uint32_t pt = lds_tpart<S, EB>(tid, wt);
+      exchange_p<S, EB>(vr, vi, lds, g, w, wt, pcur, pt);
+      w = wt;
       pcur = pt;
     }
-    // every register bit takes a butterfly; bits outside [jlo, jhi) take the
-    // identity (t = 0 gives exactly (y0, y1)).  Straight-line code: a branch
-    // per bit made the compiler copy all 16 elements after each butterfly.
+  };
+  if constexpr (kPart && REV) {
+    to_window(g.chunk[g.nchunks - 1].w);
+    butterflies<EB, PLO, PHI>(vr, vi, tn);
+  }
+  for (int i = 0; i < nloop; ++i) {
+    const Chunk ch = g.chunk[REV ? nloop - 1 - i : i];
+    to_window(ch.w);
 #pragma unroll
     for (int j = 0; j < EB; ++j) {
       const double tj = (j >= ch.jlo && j < ch.jhi) ? tn : 0.0;
@@ -579,6 +604,10 @@ __device__ __forceinline__ int apply_mixer(double (&vr)[1 << EB], double (&vi)[1
         if (!(k & (1 << j))) rx_pair_t(vr[k], vi[k], vr[k | (1 << j)], vi[k | (1 << j)], tj);
       }
     }
+  }
+  if constexpr (kPart && !REV) {
+    to_window(g.chunk[g.nchunks - 1].w);
+    butterflies<EB, PLO, PHI>(vr, vi, tn);
   }
   return w;
 }
@@ -614,7 +643,7 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
 //   FUSE   the tile's mixer gates of layer l, the phase of layer l+1, then the
 //          tile's mixer gates of layer l+1 (valid when this sweep is the last
 //          of layer l: every other gate of layer l is already applied)
-template <class S, class D, int EB, bool INIT, bool PHASE, bool EXPV, bool FUSE>
+template <class S, class D, int EB, bool INIT, bool PHASE, bool EXPV, bool FUSE, int PLO = 0, int PHI = 0>
 __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_sweep_kernel(const SweepArgs a) {
   constexpr int E = 1 << EB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -673,7 +702,7 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
   }
   const int nq = a.g.tb - a.g.act_lo;  // gates per layer in this tile
   uint32_t pcur = lds_tpart<S, EB>(tid, w);
-  w = apply_mixer<S, EB>(vr, vi, lds, a.g, tid, w, lp.tn, pcur);
+  w = apply_mixer<S, EB, false, PLO, PHI>(vr, vi, lds, a.g, tid, w, lp.tn, pcur);
   scale_tile(vr, vi, ipow(lp.ca, nq));
   if constexpr (FUSE) {
     const LayerParams lq = layer_params(a, set, 1);
@@ -684,7 +713,7 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
       load_cost<D, EB>(cv, a, base, tid, w);
     }
     phase_from_raw<S, D, EB, D::kTable>(vr, vi, cv, a, lq, tid, tab);
-    w = apply_mixer<S, EB, true>(vr, vi, lds, a.g, tid, w, lq.tn, pcur);  // ends in the load mapping
+    w = apply_mixer<S, EB, true, PLO, PHI>(vr, vi, lds, a.g, tid, w, lq.tn, pcur);  // ends in the load mapping
     scale_tile(vr, vi, ipow(lq.ca, nq));
   }
 

@@ -449,12 +449,23 @@ Args with_offsets(const Args& a, int eb) {
   return b;
 }
 
-template <class S, class D, bool INIT, bool PHASE, bool EXPV, bool FUSE = false>
+template <class S, class D, bool INIT, bool PHASE, bool EXPV, bool FUSE = false, int PLO = 0, int PHI = 0>
 void launch_sweep_f(const qk::SweepArgs& a, uint64_t blocks, uint32_t sets, hipStream_t st) {
   const uint32_t threads = 1u << (a.g.tb - kEB);
   const size_t lds = tile_lds_bytes<S, D>(a.g, threads, PHASE || FUSE);
-  hipLaunchKernelGGL((qk::qaoa_sweep_kernel<S, D, kEB, INIT, PHASE, EXPV, FUSE>), dim3((uint32_t)blocks, sets),
-                     dim3(threads), lds, st, with_offsets<S>(a, kEB));
+  hipLaunchKernelGGL((qk::qaoa_sweep_kernel<S, D, kEB, INIT, PHASE, EXPV, FUSE, PLO, PHI>),
+                     dim3((uint32_t)blocks, sets), dim3(threads), lds, st, with_offsets<S>(a, kEB));
+}
+
+// Fused sweeps (two layers' gates per launch) specialise the last chunk when
+// it holds register bits [2, 4) or [2, 3) of its window (plans end that way),
+// so its inactive bits take no identity butterflies.
+template <class S, class D>
+void launch_fused(const qk::SweepArgs& a, uint64_t blocks, uint32_t sets, hipStream_t st) {
+  const qk::Chunk last = a.g.chunk[a.g.nchunks - 1];
+  if (last.jlo == 2 && last.jhi == 4) launch_sweep_f<S, D, false, false, false, true, 2, 4>(a, blocks, sets, st);
+  else if (last.jlo == 2 && last.jhi == 3) launch_sweep_f<S, D, false, false, false, true, 2, 3>(a, blocks, sets, st);
+  else launch_sweep_f<S, D, false, false, false, true>(a, blocks, sets, st);
 }
 
 // One sweep launch.  The schedules only produce these flag combinations: the
@@ -468,7 +479,7 @@ int launch_sweep_d(const qk::SweepArgs& a, uint64_t blocks, uint32_t sets, hipSt
   if (fuse) {
     if (init || phase || expv)
       return fail(QAOA_ERR_UNSUPPORTED, "internal: sweep flag combination %d not instantiated", a.flags);
-    launch_sweep_f<S, D, false, false, false, true>(a, blocks, sets, st);
+    launch_fused<S, D>(a, blocks, sets, st);
   } else if (phase && !expv) {
     if (init) launch_sweep_f<S, D, true, true, false>(a, blocks, sets, st);
     else launch_sweep_f<S, D, false, true, false>(a, blocks, sets, st);
