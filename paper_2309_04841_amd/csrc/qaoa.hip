@@ -86,7 +86,9 @@ qk::TileGeom make_geom(int tb, int R, int hA, int qA, int qB, int act_lo, int eb
   const int rhi = lo0;
   while (rlo < rhi) {
     const int chi = std::min(rlo + eb, rhi);
-    const int w = std::max(chi - eb, std::min(rlo, qk::kLocalWin));  // w <= rlo < top_w, covers [rlo, chi)
+    // w <= rlo < top_w, covers [rlo, chi).  A short last chunk sits at the top
+    // of its window (jhi = eb), the form the fused kernels specialise.
+    const int w = (chi - rlo < eb && chi >= eb) ? chi - eb : std::max(chi - eb, std::min(rlo, qk::kLocalWin));
     g.chunk[g.nchunks++] = qk::Chunk{(int8_t)w, (int8_t)(rlo - w), (int8_t)(chi - w), 0};
     rlo = chi;
   }
@@ -457,14 +459,16 @@ void launch_sweep_f(const qk::SweepArgs& a, uint64_t blocks, uint32_t sets, hipS
                      dim3((uint32_t)blocks, sets), dim3(threads), lds, st, with_offsets<S>(a, kEB));
 }
 
-// Fused sweeps (two layers' gates per launch) specialise the last chunk when
-// it holds register bits [2, 4) or [2, 3) of its window (plans end that way),
-// so its inactive bits take no identity butterflies.
+// Fused sweeps (two layers' gates per launch) specialise a short last chunk
+// (register bits [1, 4), [2, 4) or [3, 4) of its window: plans put short last
+// chunks at the top of their window), so its other bits take no identity
+// butterflies.
 template <class S, class D>
 void launch_fused(const qk::SweepArgs& a, uint64_t blocks, uint32_t sets, hipStream_t st) {
   const qk::Chunk last = a.g.chunk[a.g.nchunks - 1];
-  if (last.jlo == 2 && last.jhi == 4) launch_sweep_f<S, D, false, false, false, true, 2, 4>(a, blocks, sets, st);
-  else if (last.jlo == 2 && last.jhi == 3) launch_sweep_f<S, D, false, false, false, true, 2, 3>(a, blocks, sets, st);
+  if (last.jhi == kEB && last.jlo == 1) launch_sweep_f<S, D, false, false, false, true, 1, 4>(a, blocks, sets, st);
+  else if (last.jhi == kEB && last.jlo == 2) launch_sweep_f<S, D, false, false, false, true, 2, 4>(a, blocks, sets, st);
+  else if (last.jhi == kEB && last.jlo == 3) launch_sweep_f<S, D, false, false, false, true, 3, 4>(a, blocks, sets, st);
   else launch_sweep_f<S, D, false, false, false, true>(a, blocks, sets, st);
 }
 
