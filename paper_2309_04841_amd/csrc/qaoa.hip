@@ -459,17 +459,16 @@ void launch_sweep_f(const qk::SweepArgs& a, uint64_t blocks, uint32_t sets, hipS
                      dim3((uint32_t)blocks, sets), dim3(threads), lds, st, with_offsets<S>(a, kEB));
 }
 
-// Fused sweeps (two layers' gates per launch) specialise a short last chunk
-// (register bits [1, 4), [2, 4) or [3, 4) of its window: plans put short last
-// chunks at the top of their window), so its other bits take no identity
-// butterflies.
-template <class S, class D>
-void launch_fused(const qk::SweepArgs& a, uint64_t blocks, uint32_t sets, hipStream_t st) {
+// Sweeps specialise a short last chunk (register bits [1, 4), [2, 4) or
+// [3, 4) of its window: plans put short last chunks at the top of their
+// window), so its other bits take no identity butterflies.
+template <class S, class D, bool INIT, bool PHASE, bool EXPV, bool FUSE>
+void launch_sweep_p(const qk::SweepArgs& a, uint64_t blocks, uint32_t sets, hipStream_t st) {
   const qk::Chunk last = a.g.chunk[a.g.nchunks - 1];
-  if (last.jhi == kEB && last.jlo == 1) launch_sweep_f<S, D, false, false, false, true, 1, 4>(a, blocks, sets, st);
-  else if (last.jhi == kEB && last.jlo == 2) launch_sweep_f<S, D, false, false, false, true, 2, 4>(a, blocks, sets, st);
-  else if (last.jhi == kEB && last.jlo == 3) launch_sweep_f<S, D, false, false, false, true, 3, 4>(a, blocks, sets, st);
-  else launch_sweep_f<S, D, false, false, false, true>(a, blocks, sets, st);
+  if (last.jhi == kEB && last.jlo == 1) launch_sweep_f<S, D, INIT, PHASE, EXPV, FUSE, 1, 4>(a, blocks, sets, st);
+  else if (last.jhi == kEB && last.jlo == 2) launch_sweep_f<S, D, INIT, PHASE, EXPV, FUSE, 2, 4>(a, blocks, sets, st);
+  else if (last.jhi == kEB && last.jlo == 3) launch_sweep_f<S, D, INIT, PHASE, EXPV, FUSE, 3, 4>(a, blocks, sets, st);
+  else launch_sweep_f<S, D, INIT, PHASE, EXPV, FUSE>(a, blocks, sets, st);
 }
 
 // One sweep launch.  The schedules only produce these flag combinations: the
@@ -483,13 +482,13 @@ int launch_sweep_d(const qk::SweepArgs& a, uint64_t blocks, uint32_t sets, hipSt
   if (fuse) {
     if (init || phase || expv)
       return fail(QAOA_ERR_UNSUPPORTED, "internal: sweep flag combination %d not instantiated", a.flags);
-    launch_fused<S, D>(a, blocks, sets, st);
+    launch_sweep_p<S, D, false, false, false, true>(a, blocks, sets, st);
   } else if (phase && !expv) {
-    if (init) launch_sweep_f<S, D, true, true, false>(a, blocks, sets, st);
-    else launch_sweep_f<S, D, false, true, false>(a, blocks, sets, st);
+    if (init) launch_sweep_p<S, D, true, true, false, false>(a, blocks, sets, st);
+    else launch_sweep_p<S, D, false, true, false, false>(a, blocks, sets, st);
   } else if (!init && !phase) {
-    if (expv) launch_sweep_f<S, D, false, false, true>(a, blocks, sets, st);
-    else launch_sweep_f<S, qk::DF64, false, false, false>(a, blocks, sets, st);  // does not read the cost vector
+    if (expv) launch_sweep_p<S, D, false, false, true, false>(a, blocks, sets, st);
+    else launch_sweep_p<S, qk::DF64, false, false, false, false>(a, blocks, sets, st);  // does not read the cost vector
   } else {
     return fail(QAOA_ERR_UNSUPPORTED, "internal: sweep flag combination %d not instantiated", a.flags);
   }
