@@ -290,6 +290,18 @@ def test_state_plans(sdt, eb):
             assert len(plan["sweeps"]) == 1
 
 
+@pytest.mark.parametrize("sdt", [_lib.QAOA_C128, _lib.QAOA_C64])
+def test_short_last_chunks_sit_at_the_window_top(sdt):
+    # the sweep kernels apply a short last chunk with specialised code when it
+    # holds the top register bits of its window (jhi = eb, jlo in 1..3)
+    for n in range(16, _lib.QAOA_MAX_QUBITS + 1):
+        plan = _lib.plan_describe(n, sdt)
+        for s in plan["sweeps"]:
+            w, jlo, jhi = s["chunks"][-1]
+            if jhi - jlo < plan["eb"]:
+                assert jhi == plan["eb"] and 1 <= jlo <= 3, (n, s["chunks"])
+
+
 @pytest.mark.parametrize("elem", [2, 4, 8])
 def test_transform_plans(elem):
     for n in range(1, _lib.QAOA_MAX_QUBITS + 1):
