@@ -168,21 +168,28 @@ def bench_batch(args):
     dg, db = torch.from_numpy(gam).to(dev), torch.from_numpy(bet).to(dev)
     states = torch.empty(batch, 1 << n, dtype=torch.complex64, device=dev)
     out = torch.empty(batch, 2, dtype=torch.float64, device=dev)
-    spp = args.sets_per_pass or tune.best_sets_per_pass(n, p, batch, diag, off, states, out, dg, db)
-    work = torch.empty(_lib.batch_workspace_bytes(n, p, batch, _lib.QAOA_C64, _lib.QAOA_DIAG_I32), dtype=torch.uint8,
-                       device=dev)
+    if args.sets_per_pass:
+        best = {"wide_tiles": _lib.get_tuning(_lib.TUNE_WIDE_TILES),
+                "fuse_layers": _lib.get_tuning(_lib.TUNE_FUSE_LAYERS), "sets_per_pass": args.sets_per_pass}
+    else:
+        best = tune.best_settings(n, p, batch, diag, off, states, out, dg, db)
+    spp = best["sets_per_pass"]
+    with tune.settings(best):
+        work = torch.empty(_lib.batch_workspace_bytes(n, p, batch, _lib.QAOA_C64, _lib.QAOA_DIAG_I32),
+                           dtype=torch.uint8, device=dev)
 
-    def run_batch():
-        _lib.qaoa_evolve_batch(n, dg, db, diag, states, diag_offset=off, out=out, sets_per_pass=spp, work=work)
+        def run_batch():
+            _lib.qaoa_evolve_batch(n, dg, db, diag, states, diag_offset=off, out=out, sets_per_pass=spp, work=work)
 
-    for _ in range(args.warmup):
-        run_batch()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        run_batch()
-    torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / args.steps
+        for _ in range(max(1, args.warmup)):
+            run_batch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            run_batch()
+        torch.cuda.synchronize()
+        t_batch = (time.perf_counter() - t0) / args.steps
+        sched = _lib.schedule_describe(n, p, _lib.QAOA_C64)
     # plain single-evaluation path, same kernels, one state at a time
     psi = torch.empty(1 << n, dtype=torch.complex64, device=dev)
     o1 = torch.empty(2, dtype=torch.float64, device=dev)
@@ -195,7 +202,7 @@ def bench_batch(args):
         q.qaoa_evolve(n, gam[s], bet[s], diag, psi, diag_offset=off, out=o1, work=w1)
     torch.cuda.synchronize()
     t_single = time.perf_counter() - t0
-    per_launch = _sweep_bytes(_lib.schedule_describe(n, p, _lib.QAOA_C64), n, 8, 4)  # one state
+    per_launch = _sweep_bytes(sched, n, 8, 4)  # one state, under the tuned schedule
     groups = -(-batch // spp)
     launches = len(per_launch) * groups  # each launch advances one group of spp states
     achieved = sum(per_launch) * batch / t_batch / 1e9
@@ -204,7 +211,8 @@ def bench_batch(args):
             "ms_per_step": 1e3 * t_batch, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f64", "data": "synthetic",
             "config": {"workload": cfg["name"], "n": n, "p": p, "sets": batch, "state": "complex64",
-                       "cost_vector": "int32", "sets_per_pass": spp},
+                       "cost_vector": "int32", "sets_per_pass": spp, "fuse_layers": best["fuse_layers"],
+                       "wide_tiles": best["wide_tiles"]},
             "single_path_evals_per_s": batch / t_single, "speedup_vs_single": t_single / t_batch,
             "roofline": {"bound": "hbm", "kernel": "qaoa_sweep_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,

@@ -153,3 +153,37 @@ def test_c3_workload_batch(q):
         assert abs(o[s, 0] - E) <= 1e-5 * abs(E)
     del states
     torch.cuda.empty_cache()
+
+
+def test_autotuned_settings_match_oracle(q, tmp_path, monkeypatch):
+    """The tuner's joint choice of tile size, layer fusion and group size runs
+    the same evaluation: every state matches the oracle under the chosen knobs,
+    and the knobs are restored afterwards."""
+    q, _lib = q
+    from paper_2309_04841_amd import tune
+    monkeypatch.setenv("QAOA_TUNE_CACHE", str(tmp_path / "tune.json"))
+    n, batch = 16, 8
+    diag, off = q.qaoa_precompute_diag(n, W.labs_terms(n), "u16", device="cuda")
+    gam, bet = W.uniform_angles(3, seed=16, batch=batch)
+    dg, db = torch.from_numpy(gam).cuda(), torch.from_numpy(bet).cuda()
+    states = torch.empty(batch, 1 << n, dtype=torch.complex128, device="cuda")
+    out = torch.empty(batch, 2, dtype=torch.float64, device="cuda")
+    before = (_lib.get_tuning(_lib.TUNE_WIDE_TILES), _lib.get_tuning(_lib.TUNE_FUSE_LAYERS))
+    best = tune.best_settings(n, 3, batch, diag, off, states, out, dg, db, reps=1)
+    assert (_lib.get_tuning(_lib.TUNE_WIDE_TILES), _lib.get_tuning(_lib.TUNE_FUSE_LAYERS)) == before
+    assert set(best) == {"wide_tiles", "fuse_layers", "sets_per_pass"} and 1 <= best["sets_per_pass"] <= batch
+    assert tune.best_settings(n, 3, batch, diag, off, states, out, dg, db) == best  # cached
+    with tune.settings(best):
+        work = torch.empty(_lib.batch_workspace_bytes(n, 3, batch, _lib.QAOA_C128, _lib.QAOA_DIAG_U16),
+                           dtype=torch.uint8, device="cuda")
+        _lib.qaoa_evolve_batch(n, dg, db, diag, states, diag_offset=off, out=out,
+                               sets_per_pass=best["sets_per_pass"], work=work)
+        torch.cuda.synchronize()
+    c = oracle.diag_labs(n).astype(np.float64)
+    got = states.cpu().numpy()
+    o = out.cpu().numpy()
+    for s in range(batch):
+        ref = oracle.evolve(n, c, gam[s], bet[s])
+        E, _ = oracle.expectation(n, ref, c)
+        assert np.linalg.norm(got[s] - ref) <= 1e-10
+        assert abs(o[s, 0] - E) <= 1e-10 * max(1.0, abs(E))
