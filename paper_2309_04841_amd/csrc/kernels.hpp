@@ -52,6 +52,7 @@ struct C128 {  // complex128: (double re, double im)
   static constexpr int kBytes = 16;
   static constexpr int kLdsBytes = 16;   // LDS bytes per tile element
   static constexpr bool kSplit = false;  // exchanges move whole elements
+  static constexpr int kAdjMinWavesPerSimd = 2;  // reverse sweeps
   static constexpr int kMaxThreads = 512;
   // 64 KiB tiles + tables: two workgroups per CU by LDS, up to 256 VGPRs.
   // (Measured: four waves per SIMD at 128 VGPRs, with split exchanges to fit
@@ -84,6 +85,7 @@ struct C64 {  // complex64 storage, FP64 arithmetic in registers
   static constexpr int kMaxThreads = 512;
   // 512-thread tiles: four waves per SIMD keep two workgroups resident per CU
   static constexpr int kMinWavesPerSimd = 4;
+  static constexpr int kAdjMinWavesPerSimd = 4;  // reverse sweeps
   __device__ static __forceinline__ void load(const void* p, uint64_t x, double& r, double& i) {
     const fvec2 v = __builtin_nontemporal_load(reinterpret_cast<const fvec2*>(p) + x);
     r = (double)v.x; i = (double)v.y;
@@ -905,12 +907,14 @@ __device__ __forceinline__ void undo_phase(double (&vr)[1 << EB], double (&vi)[1
 //   FUSE   the tile's gates of layer l undone, then layer l's gamma term and
 //          phase undo (every other gate of layer l is undone by then), then
 //          the tile's gates of layer l-1 undone
-// Four waves per SIMD (two 512-thread workgroups per CU, which the LDS
-// allows): the register cap of 128 costs some variants a few spilled bytes but
-// doubles the resident waves of the fused ones (measured: n=24 complex128
-// gradient -2.6 %, n=26 complex64 -9 % time).
+// complex64: four waves per SIMD (two 512-thread workgroups per CU, which the
+// LDS allows) double the resident waves of the fused variant, which then
+// spills 160 bytes per lane and is still faster (n=26 complex64 gradient -9 %
+// time).  complex128 keeps its registers: capped, its fused variant spilled
+// 168 bytes per lane, the spill traffic raised the measured HBM bytes per
+// launch by a third, and the gradient gained only 2.6 %.
 template <class S, class D, int EB, bool FIRST, bool PHASE, bool FUSE>
-__global__ void __launch_bounds__(512, 4) qaoa_adjoint_kernel(const AdjArgs a) {
+__global__ void __launch_bounds__(512, S::kAdjMinWavesPerSimd) qaoa_adjoint_kernel(const AdjArgs a) {
   constexpr int E = 1 << EB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   typename S::L* lds = reinterpret_cast<typename S::L*>(smem_raw);
