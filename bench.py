@@ -78,12 +78,18 @@ KERNEL_SOURCES = ("tile.hpp", "kernels.hpp", "qaoa.hip")
 
 
 def kernel_source_hash() -> str:
-    """sha256 over the HIP sources that define the sweep kernels and their launches."""
+    """sha256 over the HIP sources that define the kernels and their launches,
+    with comments and blank space removed (an edit to a comment leaves the
+    measured kernels unchanged)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2309_04841_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2309_04841_amd", "csrc", name)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

@@ -263,7 +263,8 @@ Plan adjoint_plan(int n, size_t state_bytes) { return make_plan(n, state_bytes, 
 // XY mixer plans (Section 3.2).  One layer is an ordered edge sequence
 // (ring: (i, i+1) for even i, then odd i, then the wrap edge (n-1, 0) when
 // n > 2; complete graph: (i, j), i < j, lexicographic).  A sweep applies a
-// contiguous run of it to tiles that hold all the run's qubits plus the
+// subset of the pending gates, in an order that keeps every pair of gates
+// sharing a qubit in sequence, to tiles that hold all its qubits plus the
 // passenger bits [0, pmin) for coalescing; the tile's bits must form the run
 // [0, R) and at most two more contiguous segments (the tile geometry).
 // ---------------------------------------------------------------------------
