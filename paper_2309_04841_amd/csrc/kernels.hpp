@@ -378,7 +378,7 @@ __device__ __forceinline__ void exchange_sync(bool local) {
 // Per-thread part of the swizzled LDS byte address in window w.
 template <class S, int EB>
 __device__ __forceinline__ uint32_t lds_tpart(uint32_t tid, int w) {
-  return swz<S::kLdsBytes>(thr_part<EB>(tid, w)) * S::kLdsBytes;
+  return swz<S::kLdsBytes>(thr_part<EB>(tid, w), EB) * S::kLdsBytes;
 }
 
 // Window change wf -> wt through LDS.  Linear swizzle in bytes: per-thread
@@ -1236,10 +1236,10 @@ __global__ void __launch_bounds__(512) fwht_sweep_kernel(const FwhtArgs a) {
     const Chunk ch = a.g.chunk[ci];
     if (ch.w != w) {
 #pragma unroll
-      for (int k = 0; k < E; ++k) lds[swz<sizeof(T)>(tmap<EB>(tid, k, w))] = (T)v[k];
+      for (int k = 0; k < E; ++k) lds[swz<sizeof(T)>(tmap<EB>(tid, k, w), EB)] = (T)v[k];
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < E; ++k) v[k] = (R)lds[swz<sizeof(T)>(tmap<EB>(tid, k, ch.w))];
+      for (int k = 0; k < E; ++k) v[k] = (R)lds[swz<sizeof(T)>(tmap<EB>(tid, k, ch.w), EB)];
       __syncthreads();
       w = ch.w;
     }
@@ -1259,10 +1259,10 @@ __global__ void __launch_bounds__(512) fwht_sweep_kernel(const FwhtArgs a) {
   }
   if (w != a.g.w_store) {
 #pragma unroll
-    for (int k = 0; k < E; ++k) lds[swz<sizeof(T)>(tmap<EB>(tid, k, w))] = (T)v[k];
+    for (int k = 0; k < E; ++k) lds[swz<sizeof(T)>(tmap<EB>(tid, k, w), EB)] = (T)v[k];
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < E; ++k) v[k] = (R)lds[swz<sizeof(T)>(tmap<EB>(tid, k, a.g.w_store))];
+    for (int k = 0; k < E; ++k) v[k] = (R)lds[swz<sizeof(T)>(tmap<EB>(tid, k, a.g.w_store), EB)];
     w = a.g.w_store;
   }
 #pragma unroll

@@ -58,7 +58,7 @@ struct TileGeom {
   // host (uniform across the workgroup, so the kernels read them with scalar
   // loads instead of recomputing them at every window change):
   //   goff[w][k] = tile_off(k << w): global element offset of register k
-  //   loff[w][k] = swz(k << w) * LDS entry bytes: LDS byte offset part of register k
+  //   loff[w][k] = swz(k << w, eb) * LDS entry bytes: LDS byte offset part of register k
   uint64_t goff[kMaxWin][16];
   uint32_t loff[kMaxWin][16];
 };
@@ -97,52 +97,26 @@ __device__ __forceinline__ uint64_t block_base(uint64_t b, const TileGeom& g) {
   return (lo << g.R) | (mid << (g.qA + g.hA)) | (b << topB);
 }
 
-// LDS position of tile element t: pos = t ^ L(t >> S), L linear over GF(2)
-// into the low S bits (so pos is a permutation of the tile).  The maps are
-// chosen so that every register window's access pattern is free of bank
-// conflicts (64 banks x 4 B): for 16-byte elements each group of 16 lanes, for
-// 8-byte elements each group of 32 lanes, hits distinct banks, for 16 and 8
-// elements per thread (the 16-byte map on tiles of 2^9 .. 2^12, the 8-byte map,
-// used by complex64 and the split complex128 exchanges, on 2^9 .. 2^14).  The
-// columns were found by a search over GF(2) matrices against that bank model.  Linearity also
-// splits pos(thr | k << w) = pos(thr) ^ pos(k << w) into a per-thread part and
-// a workgroup-uniform part.
+// LDS position of tile element t for tiles held as 2^eb elements per thread:
+// pos = t ^ ((t >> eb) & m), m = 31 for 8-byte entries (complex64, and the
+// split complex128 exchanges), 15 for 16-byte ones: the low bits are XORed with
+// the bits just above the register bits (a unitriangular map over GF(2), so pos
+// is a permutation of the tile).  It keeps every register window's accesses free
+// of bank conflicts on gfx950, whose LDS serves the two directions differently
+// (measured with the SQ_LDS_BANK_CONFLICT counter): ds_read_b64 serves 32 lanes
+// per cycle from 64 banks of 4 bytes, ds_write_b64 16 lanes from 32 banks,
+// ds_write_b128 8 lanes from 32 banks; the read and write counters are zero for
+// this map in every window, for 8 and 16 elements per thread.  (A map chosen
+// against the read pattern alone left 4 extra cycles on every 8-byte write in
+// windows 0, 2 and 3, and 8 on 16-byte writes in windows 1 and 2.)  Linearity
+// splits pos(thr | k << w) = pos(thr) ^ pos(k << w) into a per-thread part and a
+// workgroup-uniform part.  Cost-vector tiles (4- and 2-byte entries) use
+// pos = t ^ ((t >> 5) & 31).
 template <int ELEM_BYTES>
-struct Swz;
-template <>
-struct Swz<16> {
-  static constexpr int kShift = 4;
-  static constexpr int kCols = 8;
-  __host__ __device__ static constexpr uint32_t col(int j) {
-    constexpr uint32_t c[8] = {15, 13, 9, 14, 6, 3, 1, 9};
-    return c[j];
-  }
-};
-template <>
-struct Swz<8> {
-  static constexpr int kShift = 5;
-  static constexpr int kCols = 9;
-  __host__ __device__ static constexpr uint32_t col(int j) {
-    constexpr uint32_t c[9] = {26, 14, 19, 24, 6, 23, 3, 20, 8};
-    return c[j];
-  }
-};
-template <>
-struct Swz<4> {
-  static constexpr int kShift = 5;
-  static constexpr int kCols = 5;
-  __host__ __device__ static constexpr uint32_t col(int j) { return 1u << j; }
-};
-template <>
-struct Swz<2> : Swz<4> {};
-
-template <int ELEM_BYTES>
-__host__ __device__ __forceinline__ uint32_t swz(uint32_t t) {
-  using Z = Swz<ELEM_BYTES>;
-  uint32_t x = 0;
-#pragma unroll
-  for (int j = 0; j < Z::kCols; ++j) x ^= ((t >> (Z::kShift + j)) & 1u) ? Z::col(j) : 0u;
-  return t ^ x;
+__host__ __device__ __forceinline__ uint32_t swz(uint32_t t, int eb) {
+  if constexpr (ELEM_BYTES == 16) return t ^ ((t >> eb) & 15u);
+  else if constexpr (ELEM_BYTES == 8) return t ^ ((t >> eb) & 31u);
+  else return t ^ ((t >> 5) & 31u);
 }
 
 // Fill goff / loff for `eb` register bits and LDS entries of LDS_BYTES.
@@ -152,7 +126,7 @@ inline void fill_reg_offsets(TileGeom& g, int eb) {
     for (int k = 0; k < 16; ++k) {
       const bool used = k < (1 << eb) && w + eb <= g.tb;
       g.goff[w][k] = used ? tile_off((uint32_t)k << w, g) : 0;
-      g.loff[w][k] = used ? swz<LDS_BYTES>((uint32_t)k << w) * LDS_BYTES : 0;
+      g.loff[w][k] = used ? swz<LDS_BYTES>((uint32_t)k << w, eb) * LDS_BYTES : 0;
     }
 }
 }  // namespace qk
