@@ -656,6 +656,12 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
   const uint32_t set = blockIdx.y;
   void* psi = reinterpret_cast<char*>(a.psi) + (uint64_t)set * a.set_stride_bytes;
   const LayerParams lp = layer_params(a, set, 0);
+  // Narrow tiles (two workgroups per CU) read the next layer's parameters here,
+  // with the state loads, instead of stalling on them between the two layers
+  // (n=31 complex64 +2.6 %); the wide complex128 kernel reads them where they
+  // are used (holding them from the start cost it 2.4 %).
+  constexpr bool kEarlyNext = FUSE && !S::kSplit;
+  const LayerParams lq_early = kEarlyNext ? layer_params(a, set, 1) : lp;
 
   double vr[E], vi[E];
   const int w_load = a.g.tb - EB;
@@ -694,7 +700,7 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
   }
   if constexpr (FUSE && D::kTable) {
     // the next layer's tables go to LDS now, overlapping the state loads
-    const LayerParams lq0 = layer_params(a, set, 1);
+    const LayerParams lq0 = kEarlyNext ? lq_early : layer_params(a, set, 1);
     for (uint32_t e = tid; e < (uint32_t)kTabEntries; e += blockDim.x) tab[e] = lq0.tab[e];
   }
   if constexpr (PHASE) {
@@ -707,7 +713,7 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
   w = apply_mixer<S, EB, false, PLO, PHI>(vr, vi, lds, a.g, tid, w, lp.tn, pcur);
   scale_tile(vr, vi, ipow(lp.ca, nq));
   if constexpr (FUSE) {
-    const LayerParams lq = layer_params(a, set, 1);
+    const LayerParams lq = kEarlyNext ? lq_early : layer_params(a, set, 1);
     if constexpr (kPackedCost) {
 #pragma unroll
       for (int k = 0; k < E; ++k) cv[k] = (int32_t)((k & 1) ? (cpk[k / 2] >> 16) : (cpk[k / 2] & 0xFFFFu));
