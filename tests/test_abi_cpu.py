@@ -227,6 +227,19 @@ def test_bank_model_reproduces_measured_conflicts():
     assert extra(pair16, 8, "write") == 0 and extra(pair16, 8, "read") == 2
     assert extra(lanes * 2, 16, "write") == 8 and extra(lanes * 4, 16, "write") == 24
     assert extra(lanes, 8, "write") == extra(lanes, 8, "read") == extra(lanes, 16, "write") == 0
+    # a map searched against reads alone, pos = t ^ L(t >> 5) with these columns, read
+    # zero conflicts but 4 extra cycles per 8-byte write in window 0 (16 elements per
+    # thread) on the counter; the model must tell it from the map in use
+    cols = [26, 14, 19, 24, 6, 23, 3, 20, 8]
+
+    def old_map(t):
+        x = np.zeros_like(t)
+        for j, c in enumerate(cols):
+            x ^= ((t >> (5 + j)) & 1) * c
+        return t ^ x
+    t0 = tmap(lanes, 0, 0, 4)
+    assert extra(old_map(t0), 8, "write") == 4 and extra(old_map(t0), 8, "read") == 0
+    assert extra(swz(t0, 8, 4), 8, "write") == 0 and extra(swz(t0, 8, 4), 8, "read") == 0
 
 
 def _check_plan(n, plan, elem_bytes, emulate):
@@ -357,6 +370,31 @@ def test_headline_plans_sweep_counts():
             assert n > 14 and len(pl["sweeps"]) < len(_lib.plan_describe(n, _lib.QAOA_C64)["sweeps"]) + 1
     assert [n for n in range(15, 35) if _lib.plan_describe(n, _lib.QAOA_C128)["wide"]] == [22, 23, 24, 25, 26] + \
         list(range(31, 35))
+
+
+@pytest.mark.parametrize("elem_bytes", [8, 16])
+@pytest.mark.parametrize("eb", [3, 4])
+def test_lds_swizzle_is_a_linear_permutation(elem_bytes, eb):
+    # the kernels split pos(thr | k << w) into pos(thr) ^ pos(k << w): the map
+    # must be XOR-linear, and a permutation of every tile size it serves
+    for tb in range(eb + 1, 15):
+        t = np.arange(1 << tb)
+        pos = swz(t, elem_bytes, eb)
+        assert np.array_equal(np.sort(pos), t)
+    rng = np.random.default_rng(elem_bytes + eb)
+    a, b = rng.integers(0, 1 << 14, size=(2, 4096))
+    assert np.array_equal(swz(a ^ b, elem_bytes, eb), swz(a, elem_bytes, eb) ^ swz(b, elem_bytes, eb))
+
+
+@pytest.mark.parametrize("elem_bytes,tbmax", [(8, 14), (16, 12)])
+@pytest.mark.parametrize("eb", [3, 4])
+def test_lds_swizzle_conflict_free_in_every_window(elem_bytes, tbmax, eb):
+    # not only the windows today's plans use: every window of every multi-wave tile
+    for tb in range(eb + 6, tbmax + 1):
+        for w in range(0, tb - eb + 1):
+            for direction in ("read", "write"):
+                assert bank_conflict_degree(elem_bytes, tb, w, eb=eb, direction=direction) == 1, \
+                    (elem_bytes, tb, w, eb, direction)
 
 
 @pytest.mark.parametrize("sdt", [_lib.QAOA_C128, _lib.QAOA_C64])
