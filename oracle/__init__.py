@@ -52,6 +52,7 @@ def _load():
     P = ctypes.c_void_p
     i64 = ctypes.c_int64
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
     lib.oracle_diag_terms.argtypes = [ctypes.c_int, i64, P, P, P, P]
     lib.oracle_diag_labs.argtypes = [ctypes.c_int, P]
     lib.oracle_diag_labs_at.argtypes = [ctypes.c_int, i64, P, P]
@@ -81,6 +82,11 @@ def _ptr(a: np.ndarray):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    """Threads for the parallel loops (results do not depend on it)."""
+    _load().oracle_set_num_threads(int(t))
 
 
 def diag_terms(n: int, terms) -> np.ndarray:
@@ -140,6 +146,19 @@ def evolve(n: int, c, gamma, beta, psi0=None) -> np.ndarray:
     _load().oracle_qaoa_evolve(n, len(g), _ptr(c), _ptr(g), _ptr(b),
                                1 if psi0 is None else 0, _ptr(psi.view(np.float64)))
     return psi
+
+
+def evolve_inplace(n: int, c: np.ndarray, gamma, beta, psi: np.ndarray, init: bool) -> None:
+    """Algorithm 3 on ``psi`` (complex128[2^n], C-contiguous) in place, without
+    the copies ``evolve`` makes; ``init`` starts from |+>^n.  For states too
+    large to hold twice in host memory."""
+    g = np.ascontiguousarray(np.atleast_1d(gamma), dtype=np.float64)
+    b = np.ascontiguousarray(np.atleast_1d(beta), dtype=np.float64)
+    if (g.shape != b.shape or c.dtype != np.float64 or c.shape != (1 << n,) or psi.dtype != np.complex128
+            or psi.shape != (1 << n,)):
+        raise ValueError("shape or dtype mismatch")
+    _load().oracle_qaoa_evolve(n, len(g), _ptr(c), _ptr(g), _ptr(b), 1 if init else 0,
+                               _ptr(psi.view(np.float64)))
 
 
 def apply_phase(n: int, c, gamma: float, psi: np.ndarray) -> np.ndarray:

@@ -27,8 +27,10 @@
  *   - E is not renormalised; the squared norm is returned beside it.
  *
  * OpenMP is used on outer loops over basis states only; each output element is
- * produced by exactly the same arithmetic as in a serial run, so results do not
- * depend on the thread count (except the compensated sum, which is serial).
+ * produced by exactly the same arithmetic as in a serial run.  Sums over basis
+ * states are either serial (the compensated objective) or split into a fixed
+ * number of index ranges whose partial sums are added in range order (the
+ * gradient's inner products), so no result depends on the thread count.
  */
 #include <math.h>
 #include <stdint.h>
@@ -46,6 +48,15 @@ int oracle_num_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+void oracle_set_num_threads(int t)
+{
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
 #endif
 }
 
@@ -68,46 +79,38 @@ void oracle_diag_terms(int n, int64_t L, const double *w, const int64_t *ptr,
     }
 }
 
-/* LABS, direct definition: c(s) = sum_{k=1}^{n-1} C_k^2, C_k = sum_{i=0}^{n-k-1} s_i s_{i+k}.
+/* LABS, direct definition, at one basis state x:
+ * c(s) = sum_{k=1}^{n-1} C_k^2, C_k = sum_{i=0}^{n-k-1} s_i s_{i+k}.
  * Integer arithmetic, exact. */
+static int64_t labs_energy(int n, int64_t x)
+{
+    int64_t e = 0;
+    for (int k = 1; k < n; ++k) {
+        int64_t ck = 0;
+        for (int i = 0; i + k < n; ++i) {
+            int si = ((x >> i) & 1) ? -1 : 1;
+            int sk = ((x >> (i + k)) & 1) ? -1 : 1;
+            ck += si * sk;
+        }
+        e += ck * ck;
+    }
+    return e;
+}
+
+/* LABS for every basis state. */
 void oracle_diag_labs(int n, int64_t *c)
 {
     const int64_t N = (int64_t)1 << n;
 #pragma omp parallel for schedule(static)
-    for (int64_t x = 0; x < N; ++x) {
-        int64_t e = 0;
-        for (int k = 1; k < n; ++k) {
-            int64_t ck = 0;
-            for (int i = 0; i + k < n; ++i) {
-                int si = ((x >> i) & 1) ? -1 : 1;
-                int sk = ((x >> (i + k)) & 1) ? -1 : 1;
-                ck += si * sk;
-            }
-            e += ck * ck;
-        }
-        c[x] = e;
-    }
+    for (int64_t x = 0; x < N; ++x) c[x] = labs_energy(n, x);
 }
 
-/* LABS at selected basis states only (same definition as above), for sampled
- * checks at sizes where the full vector is too large to enumerate. */
+/* LABS at selected basis states only, for sampled checks at sizes where the
+ * full vector is too large to enumerate. */
 void oracle_diag_labs_at(int n, int64_t m, const int64_t *xs, int64_t *out)
 {
 #pragma omp parallel for schedule(static)
-    for (int64_t j = 0; j < m; ++j) {
-        const int64_t x = xs[j];
-        int64_t e = 0;
-        for (int k = 1; k < n; ++k) {
-            int64_t ck = 0;
-            for (int i = 0; i + k < n; ++i) {
-                int si = ((x >> i) & 1) ? -1 : 1;
-                int sk = ((x >> (i + k)) & 1) ? -1 : 1;
-                ck += si * sk;
-            }
-            e += ck * ck;
-        }
-        out[j] = e;
-    }
+    for (int64_t j = 0; j < m; ++j) out[j] = labs_energy(n, xs[j]);
 }
 
 /* Weighted MaxCut, direct definition in minimisation form (Section 2):
@@ -293,6 +296,33 @@ void oracle_expectation(int n, const double *psi, const double *c, double *out)
     out[1] = q + qc;
 }
 
+/* Index ranges of the gradient's inner products: the sum over x is split into
+ * GRAD_RANGES equal ranges, each summed in index order, and the range sums are
+ * added in range order, whatever the number of threads. */
+#define GRAD_RANGES 256
+
+/* sum_x Im(conj(lam_x) psi_{x ^ flip}) * (c ? c_x : 1) */
+static double im_inner(int64_t N, const double *lam, const double *psi, int64_t flip, const double *c)
+{
+    double part[GRAD_RANGES];
+    const int64_t len = (N + GRAD_RANGES - 1) / GRAD_RANGES;
+#pragma omp parallel for schedule(static)
+    for (int r = 0; r < GRAD_RANGES; ++r) {
+        const int64_t lo = (int64_t)r * len;
+        const int64_t hi = lo + len < N ? lo + len : N;
+        double s = 0.0;
+        for (int64_t x = lo; x < hi; ++x) {
+            const int64_t y = x ^ flip;
+            const double v = lam[2 * x] * psi[2 * y + 1] - lam[2 * x + 1] * psi[2 * y];
+            s += c ? c[x] * v : v;
+        }
+        part[r] = s;
+    }
+    double total = 0.0;
+    for (int r = 0; r < GRAD_RANGES; ++r) total += part[r];
+    return total;
+}
+
 /* Gradient of E = <psi_p|C|psi_p> with respect to gamma[0..p) and beta[0..p),
  * by the adjoint method (exact up to rounding):
  *   lambda = C psi_p; for l = p..1:
@@ -317,25 +347,11 @@ void oracle_qaoa_grad(int n, int p, const double *c, const double *gamma, const 
     }
     for (int l = p - 1; l >= 0; --l) {
         double sb = 0.0;
-        for (int q = 0; q < n; ++q) {
-            const int64_t bit = (int64_t)1 << q;
-            double sq = 0.0;
-#pragma omp parallel for reduction(+ : sq) schedule(static)
-            for (int64_t x = 0; x < N; ++x) {
-                const int64_t y = x ^ bit;
-                /* Im(conj(lam_x) psi_y) */
-                sq += lam[2 * x] * psi[2 * y + 1] - lam[2 * x + 1] * psi[2 * y];
-            }
-            sb += sq;
-        }
+        for (int q = 0; q < n; ++q) sb += im_inner(N, lam, psi, (int64_t)1 << q, NULL);
         out[1 + p + l] = 2.0 * sb;
         oracle_apply_mixer(n, -beta[l], psi);
         oracle_apply_mixer(n, -beta[l], lam);
-        double sg = 0.0;
-#pragma omp parallel for reduction(+ : sg) schedule(static)
-        for (int64_t x = 0; x < N; ++x)
-            sg += c[x] * (lam[2 * x] * psi[2 * x + 1] - lam[2 * x + 1] * psi[2 * x]);
-        out[1 + l] = 2.0 * sg;
+        out[1 + l] = 2.0 * im_inner(N, lam, psi, 0, c);
         oracle_apply_phase(n, c, -gamma[l], psi);
         oracle_apply_phase(n, c, -gamma[l], lam);
     }

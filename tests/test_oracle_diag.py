@@ -51,6 +51,30 @@ def test_labs_closed_forms(n):
     assert np.all(c % 2 == (n * (n - 1) // 2) % 2)
 
 
+@pytest.mark.parametrize("n", [2, 5, 9, 14])
+def test_labs_at_equals_full_vector(n):
+    # the sampled entry point returns the full vector's entries, in any order
+    rng = np.random.default_rng(n)
+    xs = np.concatenate([np.arange(1 << n), rng.integers(0, 1 << n, size=257)])
+    assert np.array_equal(oracle.diag_labs_at(n, xs), oracle.diag_labs(n)[xs])
+
+
+@pytest.mark.parametrize("n", [26, 31, 33])
+def test_labs_at_against_numpy_autocorrelation(n):
+    # sizes used by the full-size GPU checks: C_k from numpy's correlate of the
+    # spin sequence (a library routine), including indices at and above 2^32
+    rng = np.random.default_rng(1000 + n)
+    xs = np.concatenate([[0, (1 << n) - 1, (1 << n) // 3, (1 << (n - 1)) | 1],
+                         rng.integers(0, 1 << n, size=200)])
+    if n > 32:
+        xs = np.concatenate([xs, [1 << 32, (1 << 32) - 1, (1 << 32) + 12345]])
+    got = oracle.diag_labs_at(n, xs)
+    for x, e in zip(xs.tolist(), got.tolist()):
+        s = np.array([1 - 2 * ((x >> i) & 1) for i in range(n)], dtype=np.int64)
+        ac = np.correlate(s, s, mode="full")[n:]          # C_1 .. C_{n-1}
+        assert int(np.sum(ac * ac)) == e, x
+
+
 def test_labs_barker_golden():
     d = json.load(open(os.path.join(GOLD, "labs_barker.json")))
     for case in d["cases"]:

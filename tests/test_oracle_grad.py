@@ -89,3 +89,21 @@ def test_grad_zero_at_trivial_points():
     c = oracle.diag_labs(n).astype(np.float64)
     _, _, db = oracle.grad(n, c, np.zeros(p), np.array([0.3, -0.7, 1.1]))
     assert np.max(np.abs(db)) < 1e-12
+
+
+def test_grad_does_not_depend_on_thread_count():
+    # the inner products are summed over fixed index ranges in a fixed order
+    n, p = 11, 3
+    c = oracle.diag_terms(n, W.random_terms(n, 20, seed=5, max_order=4, integer=False, wmax=2.0))
+    rng = np.random.default_rng(5)
+    g, b = rng.uniform(-1, 1, size=p), rng.uniform(-1, 1, size=p)
+    saved = oracle.num_threads()
+    try:
+        results = []
+        for t in (1, 3, 8):
+            oracle.set_num_threads(t)
+            E, dg, db = oracle.grad(n, c, g, b)
+            results.append(np.concatenate([[E], dg, db]))
+    finally:
+        oracle.set_num_threads(saved)
+    assert all(np.array_equal(results[0], r) for r in results[1:])

@@ -37,9 +37,10 @@ MUTANTS = {
     "plus_state_unnormalised": ("const double a = pow(2.0, -0.5 * n);", "const double a = pow(2.0, -0.5 * (n - 1));"),
     # adjoint: gamma term taken before the mixer is undone
     "grad_gamma_before_mixer_undo": (
-        "        out[1 + p + l] = 2.0 * sb;\n        oracle_apply_mixer(n, -beta[l], psi);\n        oracle_apply_mixer(n, -beta[l], lam);\n        double sg = 0.0;",
-        "        out[1 + p + l] = 2.0 * sb;\n        double sg = 0.0;"),
-    # adjoint: conjugation on the wrong factor (sign of the beta term)
+        "        oracle_apply_mixer(n, -beta[l], psi);\n        oracle_apply_mixer(n, -beta[l], lam);\n"
+        "        out[1 + l] = 2.0 * im_inner(N, lam, psi, 0, c);",
+        "        out[1 + l] = 2.0 * im_inner(N, lam, psi, 0, c);\n"
+        "        oracle_apply_mixer(n, -beta[l], psi);\n        oracle_apply_mixer(n, -beta[l], lam);"),
     # XY gate pairs x with bit j set but forgets to clear it in the partner
     "xy_partner_keeps_bit_j": ("int64_t y = (x | bi) & ~bj;               /* y: bit i = 1, bit j = 0 */",
                                "int64_t y = (x | bi);                     /* y: bit i = 1, bit j = 0 */"),
@@ -49,8 +50,14 @@ MUTANTS = {
                                   "for (int j = n - 1; j > i; --j) { edges[2 * m] = i;"),
     "dicke_wrong_weight": ("psi[2 * x] = (__builtin_popcountll((unsigned long long)x) == k) ? a : 0.0;",
                            "psi[2 * x] = (__builtin_popcountll((unsigned long long)x) == k + 1) ? a : 0.0;"),
-    "grad_beta_conjugate": ("sq += lam[2 * x] * psi[2 * y + 1] - lam[2 * x + 1] * psi[2 * y];",
-                            "sq += lam[2 * x + 1] * psi[2 * y] - lam[2 * x] * psi[2 * y + 1];"),
+    # adjoint: conjugation on the wrong factor (sign of the beta term)
+    "grad_beta_conjugate": ("sb += im_inner(N, lam, psi, (int64_t)1 << q, NULL);",
+                            "sb -= im_inner(N, lam, psi, (int64_t)1 << q, NULL);"),
+    # adjoint: inner product pairs x with itself instead of its partner x ^ 2^q
+    "grad_beta_no_flip": ("const int64_t y = x ^ flip;", "const int64_t y = x;"),
+    # sampled LABS entry point off by one lag
+    "labs_at_wrong_lag": ("for (int64_t j = 0; j < m; ++j) out[j] = labs_energy(n, xs[j]);",
+                          "for (int64_t j = 0; j < m; ++j) out[j] = labs_energy(n - 1, xs[j]);"),
 }
 
 PINS = [
@@ -68,6 +75,8 @@ PINS = [
     lambda: XY.test_xy_layer_matches_dense_expm(5, oracle.XY_RING, XY.ring_order),
     lambda: XY.test_xy_layer_matches_dense_expm(4, oracle.XY_COMPLETE, XY.complete_order),
     lambda: XY.test_dicke_state(6, 3),
+    lambda: D.test_labs_at_equals_full_vector(9),
+    lambda: D.test_labs_at_against_numpy_autocorrelation(26),
 ]
 
 
