@@ -81,17 +81,18 @@ void oracle_diag_terms(int n, int64_t L, const double *w, const int64_t *ptr,
 
 /* LABS, direct definition, at one basis state x:
  * c(s) = sum_{k=1}^{n-1} C_k^2, C_k = sum_{i=0}^{n-k-1} s_i s_{i+k}.
+ * s_i s_{i+k} is +1 where bits i and i+k agree and -1 where they differ, so
+ * C_k = (n - k) - 2 * #{i < n-k : bit_i(x) != bit_{i+k}(x)}, the count being the
+ * population count of (x XOR x >> k) restricted to its low n - k bits (the
+ * XOR / population-count evaluation of spin products of Section 3.1).
  * Integer arithmetic, exact. */
 static int64_t labs_energy(int n, int64_t x)
 {
     int64_t e = 0;
     for (int k = 1; k < n; ++k) {
-        int64_t ck = 0;
-        for (int i = 0; i + k < n; ++i) {
-            int si = ((x >> i) & 1) ? -1 : 1;
-            int sk = ((x >> (i + k)) & 1) ? -1 : 1;
-            ck += si * sk;
-        }
+        const uint64_t low = ((uint64_t)1 << (n - k)) - 1;
+        const uint64_t differ = ((uint64_t)x ^ ((uint64_t)x >> k)) & low;
+        const int64_t ck = (int64_t)(n - k) - 2 * (int64_t)__builtin_popcountll(differ);
         e += ck * ck;
     }
     return e;

@@ -28,7 +28,9 @@ MUTANTS = {
     "phase_sign": ("double cr = cos(th), ci = -sin(th);", "double cr = cos(th), ci = sin(th);"),
     "mixer_skips_top_qubit": ("for (int q = 0; q < n; ++q) oracle_apply_rx",
                               "for (int q = 0; q + 1 < n; ++q) oracle_apply_rx"),
-    "labs_drops_last_product": ("for (int i = 0; i + k < n; ++i) {", "for (int i = 0; i + k < n - 1; ++i) {"),
+    "labs_drops_last_product": ("const uint64_t low = ((uint64_t)1 << (n - k)) - 1;",
+                                "const uint64_t low = ((uint64_t)1 << (n - k - 1)) - 1;"),
+    "labs_lag_count_off_by_one": ("const int64_t ck = (int64_t)(n - k) - 2", "const int64_t ck = (int64_t)(n - k + 1) - 2"),
     "spin_wrong_bit": ("return ((x >> i) & 1u) ? -1.0 : 1.0;", "return ((x >> (i ^ 1)) & 1u) ? -1.0 : 1.0;"),
     "maxcut_sign": ("c[x] = -cut;", "c[x] = cut;"),
     "phase_before_is_after": (
