@@ -252,7 +252,9 @@ typedef struct {
 /* arena_bytes >= 1 MiB of device memory for cost vectors and request buffers;
  * 1 <= num_streams <= 64 (default priority); 1 <= max_in_flight <= 4096. */
 int qaoa_server_create(size_t arena_bytes, int num_streams, int max_in_flight, qaoa_server **out);
-/* Finishes queued and in-flight requests, then releases everything. */
+/* Waits for the requests already running on the GPU, fails the ones still
+ * queued (never admitted) with QAOA_ERR_INVALID, then releases everything.  No
+ * qaoa_server_* call on s may overlap with or follow this one. */
 int qaoa_server_destroy(qaoa_server *s);
 /* Precompute a problem's cost vector into the arena (synchronous); terms as in
  * qaoa_precompute_diag.  Returns its id in *problem_id. */
@@ -261,7 +263,11 @@ int qaoa_server_add_problem(qaoa_server *s, int n, int64_t num_terms, const doub
                             int *problem_id);
 /* Queue one request: kind 0 = objective (result E, sum |psi|^2), kind 1 =
  * gradient (result E, dE/dgamma[p], dE/dbeta[p]); 1 <= p <= 256; host angles are
- * copied.  QAOA_ERR_NOMEM if the request could never fit the arena. */
+ * copied.  QAOA_ERR_NOMEM if the request could never fit the arena.  Requests
+ * take arena space from the bottom and cost vectors from the top; a queued
+ * request that finds no contiguous block while no other request is in flight
+ * finishes with QAOA_ERR_NOMEM (reported by qaoa_server_wait) instead of
+ * blocking the queue. */
 int qaoa_server_submit(qaoa_server *s, int problem_id, int kind, int state_dtype, int p,
                        const double *gamma, const double *beta, int64_t *ticket);
 /* Block until the request finishes; copies its result (2 or 1 + 2p doubles)

@@ -8,7 +8,10 @@
 // streams so independent requests overlap on the GPU, and retires them as their
 // completion events fire, which frees memory for the next admissions.  Every
 // request owns its buffers and the kernels reduce in a fixed order, so a
-// request's result does not depend on what else is in flight.
+// request's result does not depend on what else is in flight.  Cost vectors sit
+// at the top of the arena and requests at the bottom (arena.hpp); a request
+// that cannot be placed while nothing is in flight fails with QAOA_ERR_NOMEM
+// instead of waiting for memory that no finishing request will free.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,6 +28,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "arena.hpp"
 #include "qaoa.h"
 
 // Shared with qaoa.hip: sets the calling thread's qaoa_last_error() message.
@@ -36,60 +40,29 @@ int sfail(int code, const char* msg) { return qaoa_internal_set_error(code, msg)
 
 using Clock = std::chrono::steady_clock;
 
-// First-fit allocator over one device allocation, 256-byte granules.
+// One device allocation carved by qaoa_arena::ArenaMap.
 class Arena {
  public:
   bool init(size_t bytes) {
-    size_ = bytes & ~(size_t)255;
-    if (hipMalloc(&base_, size_) != hipSuccess) { base_ = nullptr; return false; }
-    free_[0] = size_;
+    map_.reset(bytes);
+    if (hipMalloc(&base_, map_.size()) != hipSuccess) { base_ = nullptr; return false; }
     return true;
   }
   ~Arena() {
     if (base_) (void)hipFree(base_);
   }
-  // offset or SIZE_MAX
-  size_t alloc(size_t bytes) {
-    bytes = (bytes + 255) & ~(size_t)255;
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        const size_t off = it->first, rest = it->second - bytes;
-        free_.erase(it);
-        if (rest) free_[off + bytes] = rest;
-        used_ += bytes;
-        peak_ = std::max(peak_, used_);
-        return off;
-      }
-    }
-    return SIZE_MAX;
-  }
-  void release(size_t off, size_t bytes) {
-    bytes = (bytes + 255) & ~(size_t)255;
-    used_ -= bytes;
-    auto it = free_.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
+  size_t alloc_request(size_t bytes) { return map_.alloc_low(bytes); }
+  size_t alloc_resident(size_t bytes) { return map_.alloc_high(bytes); }
+  void release(size_t off, size_t bytes) { map_.release(off, bytes); }
   char* ptr(size_t off) const { return base_ + off; }
-  size_t size() const { return size_; }
-  size_t used() const { return used_; }
-  size_t peak() const { return peak_; }
-  void reset_peak() { peak_ = used_; }
+  size_t size() const { return map_.size(); }
+  size_t used() const { return map_.used(); }
+  size_t peak() const { return map_.peak(); }
+  void reset_peak() { map_.reset_peak(); }
 
  private:
   char* base_ = nullptr;
-  size_t size_ = 0, used_ = 0, peak_ = 0;
-  std::map<size_t, size_t> free_;
+  qaoa_arena::ArenaMap map_;
 };
 
 struct Problem {
@@ -109,7 +82,7 @@ struct Request {
   size_t off = SIZE_MAX, bytes = 0;  // arena block: [out][state][adj][work]
   size_t out_len = 0;
   int slot = -1, stream = -1;
-  hipEvent_t done_ev = nullptr;
+  hipEvent_t done_ev = nullptr;  // the slot's event while in flight
   Clock::time_point t_submit, t_done;
   int status = QAOA_OK;
   std::string error;
@@ -131,6 +104,7 @@ struct qaoa_server {
   int next_stream = 0;
   int max_in_flight = 0;
   double* pinned = nullptr;  // max_in_flight slots of kSlotDoubles
+  std::vector<hipEvent_t> slot_events;  // one completion event per slot, reused
   std::vector<int> free_slots;
   std::vector<Problem> problems;
   size_t problem_bytes = 0;  // arena bytes held by resident cost vectors
@@ -143,6 +117,13 @@ struct qaoa_server {
   int64_t next_ticket = 1;
   bool stop = false;
   std::thread worker;
+
+  // Device resources (the worker thread has ended or was never started).
+  ~qaoa_server() {
+    for (auto st : streams) (void)hipStreamDestroy(st);
+    for (auto ev : slot_events) (void)hipEventDestroy(ev);
+    if (pinned) (void)hipHostFree(pinned);
+  }
 
   // stats
   uint64_t submitted = 0, completed = 0, failed = 0;
@@ -181,16 +162,18 @@ struct qaoa_server {
       rc = qaoa_grad(pr.n, r->p, r->gamma.data(), r->beta.data(), diag, pr.diag_dtype, pr.offset, pr.bytes, st_a, st_b,
                      r->state_dtype, state_bytes(pr.n, r->state_dtype), d_out, work, work_bytes, st);
     if (rc == QAOA_OK) {
+      r->done_ev = slot_events[r->slot];
       if (hipMemcpyAsync(pinned + (size_t)r->slot * kSlotDoubles, d_out, r->out_len * sizeof(double),
                          hipMemcpyDeviceToHost, st) != hipSuccess ||
-          hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming) != hipSuccess ||
-          hipEventRecord(r->done_ev, st) != hipSuccess)
+          hipEventRecord(r->done_ev, st) != hipSuccess) {
         rc = QAOA_ERR_DEVICE;
+        qaoa_internal_set_error(rc, "hipMemcpyAsync/hipEventRecord of a request failed");
+      }
     }
     if (rc != QAOA_OK) {
       r->status = rc;
       r->error = qaoa_last_error();
-      if (r->done_ev) { (void)hipEventDestroy(r->done_ev); r->done_ev = nullptr; }
+      r->done_ev = nullptr;
     }
     in_flight.push_back(r);
   }
@@ -203,10 +186,9 @@ struct qaoa_server {
     } else {
       ++failed;
     }
-    if (r->done_ev) (void)hipEventDestroy(r->done_ev);
     r->done_ev = nullptr;
-    arena.release(r->off, r->bytes);
-    free_slots.push_back(r->slot);
+    if (r->off != SIZE_MAX) arena.release(r->off, r->bytes);
+    if (r->slot >= 0) free_slots.push_back(r->slot);
     r->t_done = Clock::now();
     latencies.push_back(std::chrono::duration<double>(r->t_done - r->t_submit).count());
     last_done = r->t_done;
@@ -241,13 +223,34 @@ struct qaoa_server {
         }
       }
       if (retired) cv_done.notify_all();
+      // requests not yet admitted when the server is destroyed are dropped
+      if (stop && !queue.empty()) {
+        while (!queue.empty()) {
+          auto r = queue.front();
+          queue.pop_front();
+          r->status = QAOA_ERR_INVALID;
+          r->error = "server destroyed before the request was admitted";
+          retire(r);
+        }
+        cv_done.notify_all();
+      }
       // admit in arrival order while memory and slots allow
       while (!queue.empty() && (int)in_flight.size() < max_in_flight) {
         auto r = queue.front();
         size_t wb = 0;
         const size_t need = footprint(*r, &wb);
-        const size_t off = arena.alloc(need);
-        if (off == SIZE_MAX) break;  // wait for in-flight work to free memory
+        const size_t off = arena.alloc_request(need);
+        if (off == SIZE_MAX) {
+          if (qaoa_arena::head_blocked(in_flight.size()) == qaoa_arena::HeadAction::kWait) break;
+          // nothing in flight will free memory: fail the request rather than stall the queue
+          queue.pop_front();
+          r->status = QAOA_ERR_NOMEM;
+          r->error = "no contiguous arena block for the request (" + std::to_string(need) +
+                     " bytes) with no request in flight";
+          retire(r);
+          cv_done.notify_all();
+          continue;
+        }
         queue.pop_front();
         r->off = off;
         r->bytes = need;
@@ -285,6 +288,12 @@ int qaoa_server_create(size_t arena_bytes, int num_streams, int max_in_flight, q
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return sfail(QAOA_ERR_DEVICE, "hipStreamCreate failed");
     s->streams.push_back(st);
   }
+  for (int i = 0; i < max_in_flight; ++i) {
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+      return sfail(QAOA_ERR_DEVICE, "hipEventCreate failed");
+    s->slot_events.push_back(ev);
+  }
   s->max_in_flight = max_in_flight;
   for (int i = max_in_flight - 1; i >= 0; --i) s->free_slots.push_back(i);
   qaoa_server* raw = s.release();
@@ -301,8 +310,6 @@ int qaoa_server_destroy(qaoa_server* s) {
   }
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
-  for (auto st : s->streams) (void)hipStreamDestroy(st);
-  if (s->pinned) (void)hipHostFree(s->pinned);
   delete s;
   return QAOA_OK;
 }
@@ -318,11 +325,11 @@ int qaoa_server_add_problem(qaoa_server* s, int n, int64_t num_terms, const doub
   if (rc) return sfail(rc, qaoa_last_error());
   const size_t dbytes = ((size_t)1 << n) * diag_elem(diag_dtype);
   std::lock_guard<std::mutex> lk(s->mu);
-  const size_t off = s->arena.alloc(dbytes);
+  const size_t off = s->arena.alloc_resident(dbytes);
   if (off == SIZE_MAX) return sfail(QAOA_ERR_NOMEM, "arena has no room for the cost vector");
   size_t woff = SIZE_MAX;
   if (wb) {
-    woff = s->arena.alloc(wb);
+    woff = s->arena.alloc_resident(wb);
     if (woff == SIZE_MAX) {
       s->arena.release(off, dbytes);
       return sfail(QAOA_ERR_NOMEM, "arena has no room for the precompute workspace");

@@ -3,9 +3,13 @@ n and p, admitted by device footprint, overlapping on several streams.
 
 * every result equals the same request run alone through qaoa_evolve /
   qaoa_grad (bitwise: each request owns its buffers, reductions are fixed-order);
+* a sample of served objective and gradient results equals the FP64 oracle's
+  (complex128: 1e-10 on E, 1e-9 of the largest gradient component; complex64:
+  1e-5);
 * with an arena that fits only a few requests, all complete and the peak use
   stays within the arena (requests wait for memory instead of failing);
 * a request that can never fit is rejected at submit;
+* destroying the server with requests still queued returns (they are dropped);
 * latency percentiles are reported.
 """
 import threading
@@ -15,6 +19,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -123,3 +128,41 @@ def test_oversize_request_rejected(q):
         pid = srv.add_problem(n, W.labs_terms(n), diag_dtype="u16")
         with pytest.raises(q.QaoaError, match="NOMEM"):
             srv.submit(pid, [0.1], [0.2], dtype="complex128")
+
+
+def test_served_results_match_oracle(q):
+    probs = _problems([12, 15, 17, 13])
+    reqs = _requests(probs, 20, seed=21, pmax=8)
+    dtypes = ["complex64" if i % 2 == 0 else "complex128" for i in range(len(reqs))]
+    with q.QAOAServer(arena_bytes=1 << 30, num_streams=4, max_in_flight=8) as srv:
+        pids = [srv.add_problem(n, terms) for n, terms in probs]
+        tickets = [srv.submit(pids[k], g, b, gradient=grad, dtype=dt) for (k, g, b, grad), dt in zip(reqs, dtypes)]
+        outs = [srv.wait(t)[0] for t in tickets]
+    assert any(r[3] for r in reqs) and not all(r[3] for r in reqs)
+    for i, ((k, g, b, grad), dt, out) in enumerate(zip(reqs, dtypes, outs)):
+        n, terms = probs[k]
+        c = oracle.diag_terms(n, terms)
+        p = len(g)
+        if grad:
+            Er, dgr, dbr = oracle.grad(n, c, g, b)
+            tol = 1e-9 if dt == "complex128" else 1e-5
+            scale = max(1.0, float(np.max(np.abs(np.concatenate([dgr, dbr])))))
+            assert abs(out[0] - Er) <= tol * max(1.0, abs(Er)), i
+            assert np.max(np.abs(out[1:1 + p] - dgr)) <= tol * scale, i
+            assert np.max(np.abs(out[1 + p:1 + 2 * p] - dbr)) <= tol * scale, i
+        else:
+            Er, nrm = oracle.expectation(n, oracle.evolve(n, c, g, b), c)
+            tol = 1e-10 if dt == "complex128" else 1e-5
+            assert abs(out[0] - Er) <= tol * max(1.0, abs(Er)), i
+            assert abs(out[1] - nrm) <= tol, i
+
+
+def test_destroy_with_queued_requests_returns(q):
+    n = 20
+    srv = q.QAOAServer(arena_bytes=1 << 30, num_streams=2, max_in_flight=2)
+    pid = srv.add_problem(n, W.labs_terms(n))
+    for i in range(40):
+        srv.submit(pid, [0.1, 0.2, 0.3], [0.4, 0.5, 0.6], gradient=(i % 3 == 0))
+    t0 = time.perf_counter()
+    srv.close()  # waits for the (at most two) running requests, drops the rest
+    assert time.perf_counter() - t0 < 30.0
