@@ -181,10 +181,19 @@ uint64_t plan_blocks(int n, const qk::TileGeom& g) { return (uint64_t)1 << (n - 
 constexpr int kWideTileBits = 14;
 std::atomic<int> g_wide_tiles{1};   // QAOA_TUNE_WIDE_TILES
 std::atomic<int> g_fuse_layers{1};  // QAOA_TUNE_FUSE_LAYERS
-Plan state_plan(int n, int state_dtype) {
+
+// The knobs as one entry point sees them: read once per call and passed to
+// every step that plans, sizes or launches, so a concurrent qaoa_set_tuning
+// cannot give one call two different plans.
+struct Tuning {
+  bool wide, fuse;
+};
+Tuning tuning_now() { return Tuning{g_wide_tiles.load() != 0, g_fuse_layers.load() != 0}; }
+
+Plan state_plan(int n, int state_dtype, bool wide) {
   const size_t S = state_elem_bytes(state_dtype);
   Plan best = make_plan(n, S);
-  if (state_dtype != QAOA_C128 || n <= kWideTileBits || !g_wide_tiles.load()) return best;
+  if (state_dtype != QAOA_C128 || n <= kWideTileBits || !wide) return best;
   for (size_t run : {(size_t)128, (size_t)64}) {
     Plan w = make_plan(n, S, kEB, kWideTileBits, run);
     if (w.sweeps.size() < best.sweeps.size()) {
@@ -211,9 +220,9 @@ struct SweepStep {
 // sweep order; the last sweep of layer l > 0 also undoes layer l's phase (all
 // of layer l's gates are undone by then) and layer l-1's gates on the same
 // qubits.  `layer` is the layer undone first; flags are qk::A_*.
-std::vector<SweepStep> adjoint_schedule(int nsw, int p) {
+std::vector<SweepStep> adjoint_schedule(int nsw, int p, bool fuse) {
   std::vector<SweepStep> out;
-  if (!g_fuse_layers.load()) {  // layers p-1..0, sweeps nsw-1..0, phase undone in sweep 0
+  if (!fuse) {  // layers p-1..0, sweeps nsw-1..0, phase undone in sweep 0
     for (int l = p - 1; l >= 0; --l)
       for (int sw = nsw - 1; sw >= 0; --sw)
         out.push_back(SweepStep{sw, l, (l == p - 1 && sw == nsw - 1 ? qk::A_FIRST : 0) | (sw == 0 ? qk::A_PHASE : 0)});
@@ -232,9 +241,9 @@ std::vector<SweepStep> adjoint_schedule(int nsw, int p) {
   return out;
 }
 
-std::vector<SweepStep> sweep_schedule(int nsw, int p, bool init, bool expv) {
+std::vector<SweepStep> sweep_schedule(int nsw, int p, bool init, bool expv, bool fuse) {
   std::vector<SweepStep> out;
-  if (!g_fuse_layers.load()) {  // every layer in plan order, phase in its first sweep
+  if (!fuse) {  // every layer in plan order, phase in its first sweep
     for (int l = 0; l < p; ++l)
       for (int sw = 0; sw < nsw; ++sw) {
         int flags = sw == 0 ? qk::F_PHASE | ((l == 0 && init) ? qk::F_INIT : 0) : 0;
@@ -750,9 +759,11 @@ struct EvolveWork {
 };
 EvolveWork evolve_work(int n, size_t states, size_t rows, int state_dtype) {
   EvolveWork b{};
-  const Plan pl = state_plan(n, state_dtype);
-  uint64_t last = 0;  // most workgroups of any sweep (the last sweep depends on p)
-  for (const auto& g : pl.sweeps) last = std::max(last, plan_blocks(n, g));
+  // most workgroups of any sweep of either plan (the last sweep depends on p,
+  // the plan on the wide-tile knob), so the size does not depend on the knobs
+  uint64_t last = 0;
+  for (bool wide : {false, true})
+    for (const auto& g : state_plan(n, state_dtype, wide).sweeps) last = std::max(last, plan_blocks(n, g));
   b.partials_stride = 2 * std::max<uint64_t>(last, kExpectBlocks);
   b.partials_bytes = sizeof(double) * b.partials_stride * states;
   b.pset_bytes = ((qk::kParamRow * sizeof(double) * rows + 255) / 256) * 256;
@@ -1049,7 +1060,7 @@ static int enqueue_expectation(int n, const void* d_state, int sdt, const void* 
 static int enqueue_evolve(int n, int p, int batch, const double* h_gamma, const double* h_beta, const double* d_gamma,
                           const double* d_beta, const void* d_diag, int diag_dtype, double diag_offset,
                           void* d_states, int state_dtype, int init, double* d_out, int G, void* d_work,
-                          hipStream_t st) {
+                          Tuning tn, hipStream_t st) {
   const uint64_t N = (uint64_t)1 << n;
   const size_t S = state_elem_bytes(state_dtype);
   const bool host_angles = (h_gamma != nullptr);
@@ -1081,7 +1092,7 @@ static int enqueue_evolve(int n, int p, int batch, const double* h_gamma, const 
     LAUNCH_CHECK("layer_prep_kernel");
   }
 
-  const Plan pl = state_plan(n, state_dtype);
+  const Plan pl = state_plan(n, state_dtype, tn.wide);
   qk::SweepArgs a{};
   a.diag = d_diag;
   a.diag_offset = diag_offset;
@@ -1092,7 +1103,8 @@ static int enqueue_evolve(int n, int p, int batch, const double* h_gamma, const 
   a.set_stride_bytes = N * S;
   a.partials_stride = ew.partials_stride;
   const std::vector<SweepStep> sched =
-      pl.single ? std::vector<SweepStep>() : sweep_schedule((int)pl.sweeps.size(), p, init != 0, d_out != nullptr);
+      pl.single ? std::vector<SweepStep>()
+                : sweep_schedule((int)pl.sweeps.size(), p, init != 0, d_out != nullptr, tn.fuse);
   int rc = QAOA_OK;
   for (int s0 = 0; s0 < batch; s0 += G) {
     const uint32_t sets = (uint32_t)std::min(G, batch - s0);
@@ -1167,7 +1179,7 @@ int qaoa_evolve(int n, int p, const double* gamma, const double* beta, const voi
   }
 
   return enqueue_evolve(n, p, 1, gamma, beta, nullptr, nullptr, d_diag, diag_dtype, diag_offset, d_state, state_dtype,
-                        init, d_out, 1, d_work, st);
+                        init, d_out, 1, d_work, tuning_now(), st);
 }
 
 int qaoa_expectation(int n, const void* d_state, int state_dtype, size_t state_bytes, const void* d_diag,
@@ -1234,7 +1246,7 @@ int qaoa_evolve_batch(int n, int p, int batch, const double* d_gamma, const doub
     return QAOA_OK;
   }
   return enqueue_evolve(n, p, batch, nullptr, nullptr, d_gamma, d_beta, d_diag, diag_dtype, diag_offset, d_states,
-                        state_dtype, init, d_out, G, d_work, st);
+                        state_dtype, init, d_out, G, d_work, tuning_now(), st);
 }
 
 int qaoa_plan_describe(int kind, int n, int state_dtype, int elem_bytes, int* out, int cap) {
@@ -1242,7 +1254,7 @@ int qaoa_plan_describe(int kind, int n, int state_dtype, int elem_bytes, int* ou
   Plan pl;
   if (kind == 0 || kind == 1) {
     if (!valid_state_dtype(state_dtype)) return -fail(QAOA_ERR_INVALID, "bad state dtype %d", state_dtype);
-    pl = kind == 0 ? state_plan(n, state_dtype) : adjoint_plan(n, state_elem_bytes(state_dtype));
+    pl = kind == 0 ? state_plan(n, state_dtype, tuning_now().wide) : adjoint_plan(n, state_elem_bytes(state_dtype));
   } else if (kind == 2) {
     if (elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8) return -fail(QAOA_ERR_INVALID, "bad elem_bytes");
     pl = make_plan(n, (size_t)elem_bytes);
@@ -1269,10 +1281,12 @@ int qaoa_schedule_describe(int kind, int n, int p, int state_dtype, int init, in
   if (p < 0) return -fail(QAOA_ERR_INVALID, "p < 0");
   if (!valid_state_dtype(state_dtype)) return -fail(QAOA_ERR_INVALID, "bad state dtype %d", state_dtype);
   const size_t S = state_elem_bytes(state_dtype);
-  const Plan pl = kind == 0 ? state_plan(n, state_dtype) : adjoint_plan(n, S);
+  const Tuning tn = tuning_now();
+  const Plan pl = kind == 0 ? state_plan(n, state_dtype, tn.wide) : adjoint_plan(n, S);
   if (pl.single) return 0;
-  const std::vector<SweepStep> sched = kind == 0 ? sweep_schedule((int)pl.sweeps.size(), p, init != 0, reduce != 0)
-                                                 : adjoint_schedule((int)pl.sweeps.size(), p);
+  const std::vector<SweepStep> sched = kind == 0
+                                           ? sweep_schedule((int)pl.sweeps.size(), p, init != 0, reduce != 0, tn.fuse)
+                                           : adjoint_schedule((int)pl.sweeps.size(), p, tn.fuse);
   int i = 0;
   for (const auto& s : sched) {
     const int v[3] = {s.sweep, s.layer, s.flags};
@@ -1460,11 +1474,12 @@ int qaoa_grad(int n, int p, const double* gamma, const double* beta, const void*
   if (!d_work || work_bytes < gw.total) return fail(QAOA_ERR_NOMEM, "workspace too small: need %zu bytes", gw.total);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   char* wk = reinterpret_cast<char*>(d_work);
+  const Tuning tn = tuning_now();
 
   // forward pass: psi_p in d_state, (E, norm) in d_out[0..1] (d_out[1] is
   // overwritten by the gradient below)
   rc = enqueue_evolve(n, p, 1, gamma, beta, nullptr, nullptr, d_diag, diag_dtype, diag_offset, d_state, state_dtype, 1,
-                      d_out, 1, d_work, st);
+                      d_out, 1, d_work, tn, st);
   if (rc) return rc;
 
   // parameter rows and tables of all p layers
@@ -1505,7 +1520,7 @@ int qaoa_grad(int n, int p, const double* gamma, const double* beta, const void*
   } else {
     blocks = plan_blocks(n, pl.sweeps[0]);
     auto slot = [&](int l, int sw) { return rev + (size_t)l * gw.layer_stride + (size_t)sw * blocks * 2; };
-    for (const SweepStep& stp : adjoint_schedule(nsw, p)) {
+    for (const SweepStep& stp : adjoint_schedule(nsw, p, tn.fuse)) {
       a.layer = stp.layer;
       a.g = pl.sweeps[stp.sweep];
       a.partials = slot(stp.layer, stp.sweep);
