@@ -24,7 +24,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-METRIC = "QAOA expectation evals/s, LABS n=26 p=10"
+METRIC = "QAOA expectation evals/s, LABS n=26 p=10; % HBM peak; served p50/p99"
 
 CONFIGS = {
     # LABS energies are integers in [0, sum_k (n-k)^2] (12529 at n=34), so uint16 holds the cost
@@ -126,24 +126,33 @@ def cpu_baseline(cfg, budget_s=12.0, mixer=None):
     n, p = cfg["n"], cfg["p"]
     xy_kind = {None: None, "xy_ring": oracle.XY_RING, "xy_complete": oracle.XY_COMPLETE}[mixer]
     t0 = time.perf_counter()
-    c = oracle.diag_labs(n).astype(np.float64)
+    c = oracle.diag_labs(n)
+    c = c.astype(np.float64)
     t_diag = time.perf_counter() - t0
-    plus = np.full(1 << n, 2.0 ** (-n / 2), dtype=np.complex128)
-    psi = plus
     layers = 0
-    t0 = time.perf_counter()
-    while True:
-        l = layers % p
-        if l == 0:
-            psi = plus.copy()
-        psi = oracle.apply_phase(n, c, cfg["gamma"][l], psi)
-        if xy_kind is None:
-            psi = oracle.apply_mixer(n, cfg["beta"][l], psi)
-        else:
+    if xy_kind is None:
+        # Algorithm 3 one layer at a time on one state (no copies: at n=31 it holds 32 GiB)
+        psi = np.empty(1 << n, dtype=np.complex128)
+        t0 = time.perf_counter()
+        while True:
+            l = layers % p
+            oracle.evolve_inplace(n, c, cfg["gamma"][l:l + 1], cfg["beta"][l:l + 1], psi, init=(l == 0))
+            layers += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
+    else:
+        plus = np.full(1 << n, 2.0 ** (-n / 2), dtype=np.complex128)
+        psi = plus
+        t0 = time.perf_counter()
+        while True:
+            l = layers % p
+            if l == 0:
+                psi = plus.copy()
+            psi = oracle.apply_phase(n, c, cfg["gamma"][l], psi)
             psi = oracle.apply_xy_mixer(n, xy_kind, cfg["beta"][l], psi)
-        layers += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
+            layers += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
     t_layers = time.perf_counter() - t0
     evals_per_s = layers / (t_layers * p)
     return dict(value=evals_per_s, unit="evals/s", cores=oracle.num_threads(), kind="oracle",
@@ -155,10 +164,24 @@ def cpu_baseline(cfg, budget_s=12.0, mixer=None):
                        f"{t_diag:.2f} s and excluded like the GPU precompute")
 
 
+def _replay_ms(graph, steps, stream):
+    """Average time of one replay of a captured graph, HIP events on `stream`."""
+    import torch
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record(stream)
+    for _ in range(steps):
+        graph.replay()
+    e.record(stream)
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / steps
+
+
 def bench_batch(args):
     """Batched parameter sweep: weighted MaxCut G(22, 0.3), p=6, 512 (gamma, beta)
-    sets, complex64, one qaoa_evolve_batch call (graph-replayable) vs a loop of
-    single qaoa_evolve calls on the same GPU."""
+    sets, complex64.  The batched call and, for comparison, the loop of 512
+    single qaoa_evolve calls are each captured once in a HIP graph and timed by
+    replaying it (one submission per batch); eager timings are reported beside."""
     import numpy as np
     import torch
 
@@ -170,6 +193,7 @@ def bench_batch(args):
     gam, bet = cfg["gamma"], cfg["beta"]
     batch = gam.shape[0]
     dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
     diag, off = q.qaoa_precompute_diag(n, cfg["terms"], "i32", device=dev)
     dg, db = torch.from_numpy(gam).to(dev), torch.from_numpy(bet).to(dev)
     states = torch.empty(batch, 1 << n, dtype=torch.complex64, device=dev)
@@ -180,6 +204,9 @@ def bench_batch(args):
     else:
         best = tune.best_settings(n, p, batch, diag, off, states, out, dg, db)
     spp = best["sets_per_pass"]
+    psi = torch.empty(1 << n, dtype=torch.complex64, device=dev)
+    o1 = torch.empty(batch, 2, dtype=torch.float64, device=dev)
+    w1 = _lib.alloc_workspace(_lib.QAOA_OP_EVOLVE, n, _lib.QAOA_C64, _lib.QAOA_DIAG_I32, dev)
     with tune.settings(best):
         work = torch.empty(_lib.batch_workspace_bytes(n, p, batch, _lib.QAOA_C64, _lib.QAOA_DIAG_I32),
                            dtype=torch.uint8, device=dev)
@@ -187,43 +214,56 @@ def bench_batch(args):
         def run_batch():
             _lib.qaoa_evolve_batch(n, dg, db, diag, states, diag_offset=off, out=out, sets_per_pass=spp, work=work)
 
+        def run_singles():
+            for s_ in range(batch):
+                q.qaoa_evolve(n, gam[s_], bet[s_], diag, psi, diag_offset=off, out=o1[s_], work=w1)
+
         for _ in range(max(1, args.warmup)):
             run_batch()
+        run_singles()
         torch.cuda.synchronize()
+        ref_out = out.clone()
+        # eager: one library call per batch / per set
         t0 = time.perf_counter()
         for _ in range(args.steps):
             run_batch()
         torch.cuda.synchronize()
-        t_batch = (time.perf_counter() - t0) / args.steps
+        t_batch_eager = (time.perf_counter() - t0) / args.steps
+        t0 = time.perf_counter()
+        run_singles()
+        torch.cuda.synchronize()
+        t_single_eager = time.perf_counter() - t0
+        # captured: one graph replay per batch (kernels only, so the call is capturable)
+        g_batch, g_single = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g_batch):
+            run_batch()
+        with torch.cuda.graph(g_single):
+            run_singles()
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream(dev)
+        ms_batch = _replay_ms(g_batch, args.steps, stream)
+        ms_single = _replay_ms(g_single, max(1, args.steps // 4), stream)
+        if not (torch.equal(out, ref_out) and torch.equal(o1, ref_out)):
+            raise RuntimeError("graph replay, eager batch and single calls disagree")
         sched = _lib.schedule_describe(n, p, _lib.QAOA_C64)
-    # plain single-evaluation path, same kernels, one state at a time
-    psi = torch.empty(1 << n, dtype=torch.complex64, device=dev)
-    o1 = torch.empty(2, dtype=torch.float64, device=dev)
-    w1 = _lib.alloc_workspace(_lib.QAOA_OP_EVOLVE, n, _lib.QAOA_C64, _lib.QAOA_DIAG_I32, dev)
-    for s in range(4):
-        q.qaoa_evolve(n, gam[s], bet[s], diag, psi, diag_offset=off, out=o1, work=w1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(batch):
-        q.qaoa_evolve(n, gam[s], bet[s], diag, psi, diag_offset=off, out=o1, work=w1)
-    torch.cuda.synchronize()
-    t_single = time.perf_counter() - t0
+    t_batch = ms_batch * 1e-3
     per_launch = _sweep_bytes(sched, n, 8, 4)  # one state, under the tuned schedule
     groups = -(-batch // spp)
     launches = len(per_launch) * groups  # each launch advances one group of spp states
     achieved = sum(per_launch) * batch / t_batch / 1e9
     return {"metric": "batched QAOA evals/s, weighted MaxCut G(22,0.3) p=6, 512 sets", "value": batch / t_batch,
             "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-            "ms_per_step": 1e3 * t_batch, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "ms_per_step": ms_batch, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f64", "data": "synthetic",
             "config": {"workload": cfg["name"], "n": n, "p": p, "sets": batch, "state": "complex64",
                        "cost_vector": "int32", "sets_per_pass": spp, "fuse_layers": best["fuse_layers"],
-                       "wide_tiles": best["wide_tiles"]},
-            "single_path_evals_per_s": batch / t_single, "speedup_vs_single": t_single / t_batch,
+                       "wide_tiles": best["wide_tiles"], "timing": "HIP graph replay"},
+            "single_path_evals_per_s": batch / (ms_single * 1e-3), "speedup_vs_single": ms_single / ms_batch,
+            "eager_batch_evals_per_s": batch / t_batch_eager, "eager_single_evals_per_s": batch / t_single_eager,
             "roofline": {"bound": "hbm", "kernel": "qaoa_sweep_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                          "bytes_per_launch": sum(per_launch) * batch / launches, "launches_per_step": launches,
-                         "avg_launch_ms": 1e3 * t_batch / launches}}
+                         "avg_launch_ms": ms_batch / launches}}
 
 
 def _adjoint_bytes(sched, n, state_bytes, diag_bytes):
@@ -325,67 +365,168 @@ def bench_grad(args):
     return res
 
 
-def bench_serve(args):
-    """Served mix: Poisson arrivals at --rate, 60% objective / 40% gradient,
-    LABS or 3-regular (odd n: 4-regular) MaxCut with n ~ U{16..30}, p ~ U{1..20}, complex64;
-    p50/p99 latency and requests/s, vs the same requests run one at a time."""
+SERVE_MIXES = {
+    # the configured serving workload: n ~ U{16..30}, p ~ U{1..20}
+    "mix": dict(ns=range(16, 31), pmax=20, count=96),
+    # requests small enough that one does not fill the GPU (n ~ U{16..22}):
+    # the case where overlapping admitted requests pays
+    "small": dict(ns=range(16, 23), pmax=20, count=600),
+}
+
+
+def _serve_workload(name, seed):
+    """Problems and requests of a serving mix: 60 % objective / 40 % gradient,
+    LABS or regular MaxCut (3-regular for even n, 4-regular for odd n)."""
+    import numpy as np
+
+    import workloads as W
+    spec = SERVE_MIXES[name]
+    rng = np.random.default_rng(seed)
+    probs = {}
+    for n in spec["ns"]:
+        probs[("labs", n)] = (n, W.labs_terms(n))
+        d = 3 if n % 2 == 0 else 4  # d n must be even
+        probs[("maxcut", n)] = (n, W.maxcut_terms(W.random_regular_graph(d, n, seed=100 + n)))
+    keys = list(probs)
+    reqs = []
+    for _ in range(spec["count"]):
+        k = keys[int(rng.integers(0, len(keys)))]
+        p = int(rng.integers(1, spec["pmax"] + 1))
+        reqs.append((k, rng.uniform(0, 1, size=p), rng.uniform(0, np.pi, size=p), bool(rng.random() < 0.4)))
+    return probs, reqs
+
+
+def _serve_run(probs, reqs, arrivals=None, streams=4, max_in_flight=16, arena_bytes=160 << 30):
+    """Run the requests through a fresh server; `arrivals` (seconds from the
+    start) paces the submissions, None submits them all at once.  Returns the
+    server's stats, the wall time from the first submission to the last result,
+    and the results in request order."""
     import threading
 
+    import paper_2309_04841_amd as q
+    srv = q.QAOAServer(arena_bytes=arena_bytes, num_streams=streams, max_in_flight=max_in_flight)
+    try:
+        pids = {k: srv.add_problem(n, terms) for k, (n, terms) in probs.items()}
+        tickets = []
+
+        def submitter():
+            t0 = time.perf_counter()
+            for i, (k, g, b, grad) in enumerate(reqs):
+                if arrivals is not None:
+                    dt = arrivals[i] - (time.perf_counter() - t0)
+                    if dt > 0:
+                        time.sleep(dt)
+                tickets.append(srv.submit(pids[k], g, b, gradient=grad))
+
+        t0 = time.perf_counter()
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+        results = [srv.wait(t)[0] for t in tickets]
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    finally:
+        srv.close()
+    return st, wall, results
+
+
+def serve_summary(name, seed=7, load=0.6):
+    """Capacity (all requests submitted at once, four streams, 16 in flight),
+    one-at-a-time rate (one stream, one in flight), and latency under Poisson
+    arrivals at `load` times the capacity, where the queue stays bounded."""
+    import numpy as np
+    probs, reqs = _serve_workload(name, seed)
+    _serve_run(probs, reqs[:8])  # warm the kernels and the allocator
+    st_cap, wall_cap, _ = _serve_run(probs, reqs)
+    capacity = len(reqs) / wall_cap
+    _, wall_seq, _ = _serve_run(probs, reqs, streams=1, max_in_flight=1)
+    sequential = len(reqs) / wall_seq
+    rate = load * capacity
+    arrivals = np.cumsum(np.random.default_rng(seed + 1).exponential(1.0 / rate, size=len(reqs)))
+    st, wall, _ = _serve_run(probs, reqs, arrivals=arrivals)
+    spec = SERVE_MIXES[name]
+    return {"requests": len(reqs), "n_range": [min(spec["ns"]), max(spec["ns"])], "p_range": [1, spec["pmax"]],
+            "capacity_requests_per_s": capacity, "sequential_requests_per_s": sequential,
+            "overlap_gain": capacity / sequential, "offered_requests_per_s": rate,
+            "served_requests_per_s": len(reqs) / wall, "p50_ms": 1e3 * st["p50_s"], "p99_ms": 1e3 * st["p99_s"],
+            "mean_ms": 1e3 * st["mean_s"], "max_ms": 1e3 * st["max_s"],
+            "peak_arena_GB": max(st["peak_bytes"], st_cap["peak_bytes"]) / 1e9}
+
+
+def bench_serve(args):
+    """Served mixes (60 % objective / 40 % gradient, LABS or regular MaxCut,
+    complex64): capacity, one-at-a-time rate, and p50/p99 latency of Poisson
+    arrivals at 0.6 of capacity; n ~ U{16..30} and the small-request mix
+    n ~ U{16..22}."""
+    mixes = {name: serve_summary(name) for name in SERVE_MIXES}
+    main_mix = mixes["mix"]
+    return {"metric": "served QAOA requests/s (60% objective / 40% gradient, n 16..30, p 1..20)",
+            "value": main_mix["capacity_requests_per_s"], "unit": "requests/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "serve_mix", "state": "complex64", "streams": 4, "max_in_flight": 16},
+            "p50_ms": main_mix["p50_ms"], "p99_ms": main_mix["p99_ms"], "mixes": mixes}
+
+
+MALL_BYTES = 256 << 20  # memory-side (Infinity) cache of one MI355X
+
+
+def bench_layer_curve(args):
+    """Time per QAOA layer against n (LABS, uint16 cost vector, linear ramp),
+    complex128 n = 18..32 and complex64 n = 18..33: per-layer time
+    (T(p=10) - T(p=2)) / 8 removes the fixed first and last launches and the
+    parameter preparation; its algorithmic bytes come from the same schedules.
+    Flags the sizes whose state and cost vector fit the 256 MB memory-side
+    cache (bandwidth there can exceed HBM's)."""
     import numpy as np
     import torch
 
     import paper_2309_04841_amd as q
+    from paper_2309_04841_amd import _lib
     import workloads as W
-    rng = np.random.default_rng(7)
-    ns = list(range(16, 31))
-    srv = q.QAOAServer(arena_bytes=160 << 30, num_streams=4, max_in_flight=16)
-    probs = {}
-    for n in ns:
-        probs[("labs", n)] = (n, W.labs_terms(n))
-        d = 3 if n % 2 == 0 else 4  # d n must be even
-        probs[("maxcut", n)] = (n, W.maxcut_terms(W.random_regular_graph(d, n, seed=100 + n)))
-    pids = {k: srv.add_problem(n, terms) for k, (n, terms) in probs.items()}
-    keys = list(probs)
-    reqs = []
-    for _ in range(args.requests):
-        k = keys[int(rng.integers(0, len(keys)))]
-        p = int(rng.integers(1, 21))
-        reqs.append((k, rng.uniform(0, 1, size=p), rng.uniform(0, np.pi, size=p), bool(rng.random() < 0.4)))
-    arrivals = np.cumsum(rng.exponential(1.0 / args.rate, size=len(reqs)))
-    tickets = []
-
-    def submitter():
-        t0 = time.perf_counter()
-        for (k, g, b, grad), ta in zip(reqs, arrivals):
-            dt = ta - (time.perf_counter() - t0)
-            if dt > 0:
-                time.sleep(dt)
-            tickets.append(srv.submit(pids[k], g, b, gradient=grad))
-
-    t0 = time.perf_counter()
-    th = threading.Thread(target=submitter)
-    th.start()
-    th.join()
-    for t in tickets:
-        srv.wait(t)
-    wall = time.perf_counter() - t0
-    st = srv.stats()
-    # the same requests, one at a time (max_in_flight = 1, same server path)
-    srv.close()
-    seq = q.QAOAServer(arena_bytes=160 << 30, num_streams=1, max_in_flight=1)
-    spids = {k: seq.add_problem(n, terms) for k, (n, terms) in probs.items()}
-    t1 = time.perf_counter()
-    for k, g, b, grad in reqs:
-        seq.wait(seq.submit(spids[k], g, b, gradient=grad))
-    t_seq = time.perf_counter() - t1
-    seq.close()
-    return {"metric": "served QAOA requests/s (60% objective / 40% gradient, n 16..30, p 1..20)",
-            "value": st["completed"] / wall, "unit": "requests/s", "n_gpus": 1, "higher_is_better": True,
-            "dtype": "f64", "data": "synthetic",
-            "config": {"workload": "serve_mix", "requests": len(reqs), "rate_per_s": args.rate, "state": "complex64",
-                       "streams": 4, "max_in_flight": 16},
-            "p50_ms": 1e3 * st["p50_s"], "p99_ms": 1e3 * st["p99_s"], "mean_ms": 1e3 * st["mean_s"],
-            "peak_arena_GB": st["peak_bytes"] / 1e9, "sequential_requests_per_s": len(reqs) / t_seq}
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    rows = []
+    for dtype, sdt, S, ns in (("complex128", torch.complex128, 16, range(18, 33)),
+                              ("complex64", torch.complex64, 8, range(18, 34))):
+        for n in ns:
+            gamma, beta = W.linear_ramp(10, seed=n)
+            diag, off = q.qaoa_precompute_diag(n, W.labs_terms(n), "u16", device=dev)
+            psi = torch.empty(1 << n, dtype=sdt, device=dev)
+            out = torch.empty(2, dtype=torch.float64, device=dev)
+            work = _lib.alloc_workspace(_lib.QAOA_OP_EVOLVE, n, _lib.state_dtype_code(psi), _lib.QAOA_DIAG_U16, dev)
+            reps = 3 if n >= 30 else 10
+            t = {}
+            for p in (2, 10):
+                g, b = gamma[:p], beta[:p]
+                q.qaoa_evolve(n, g, b, diag, psi, diag_offset=off, out=out, work=work)
+                s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                s0.record(stream)
+                for _ in range(reps):
+                    q.qaoa_evolve(n, g, b, diag, psi, diag_offset=off, out=out, work=work)
+                s1.record(stream)
+                torch.cuda.synchronize()
+                t[p] = s0.elapsed_time(s1) / reps
+            code = _lib.state_dtype_code(psi)
+            plan = _lib.plan_describe(n, code)
+            if plan["single"]:
+                b_layer = None
+            else:
+                b2 = sum(_sweep_bytes(_lib.schedule_describe(n, 2, code), n, S, 2))
+                b10 = sum(_sweep_bytes(_lib.schedule_describe(n, 10, code), n, S, 2))
+                b_layer = (b10 - b2) / 8
+            ms_layer = (t[10] - t[2]) / 8
+            gbs = b_layer / (ms_layer * 1e-3) / 1e9 if b_layer else None
+            rows.append({"state": dtype, "n": n, "sweeps_per_layer": len(plan["sweeps"]), "wide": plan["wide"],
+                         "ms_per_layer": ms_layer, "ms_eval_p10": t[10], "bytes_per_layer": b_layer,
+                         "GBps": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS if gbs else None,
+                         "mall_resident": (1 << n) * (S + 2) <= MALL_BYTES})
+            print(f"layer_curve {dtype} n={n} {ms_layer:.4f} ms/layer", file=sys.stderr, flush=True)
+            del psi, diag, work
+            torch.cuda.empty_cache()
+    return {"metric": "time per QAOA layer vs n, LABS, uint16 cost vector", "unit": "ms/layer",
+            "higher_is_better": False, "n_gpus": 1, "data": "synthetic", "rows": rows}
 
 
 def main(argv=None):
@@ -393,10 +534,9 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", choices=sorted(CONFIGS) + ["batch", "serve", "grad"], default="labs26")
+    ap.add_argument("--config", choices=sorted(CONFIGS) + ["batch", "serve", "grad", "layer_curve"],
+                    default="labs26")
     ap.add_argument("--sets-per-pass", type=int, default=0, help="batch: states advanced together (0 = autotune)")
-    ap.add_argument("--requests", type=int, default=120, help="serve: number of requests")
-    ap.add_argument("--rate", type=float, default=40.0, help="serve: Poisson arrival rate (requests/s)")
     ap.add_argument("--wide-tiles", type=int, choices=(0, 1), default=1,
                     help="complex128: 2^14-element tiles when they save a sweep (library tuning knob)")
     ap.add_argument("--fuse-layers", type=int, choices=(0, 1), default=1,
@@ -404,6 +544,9 @@ def main(argv=None):
     ap.add_argument("--diag", choices=("u16", "i32", "f64"), default=None,
                     help="cost-vector storage (default: the configuration's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="labs26: skip the nested complex64 n=31 evaluation and the served mixes")
+    ap.add_argument("--c2b-steps", type=int, default=10, help="labs26: timed evaluations of the nested n=31 run")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (torch), the reference for HBM counter scaling")
@@ -420,9 +563,10 @@ def main(argv=None):
         print(json.dumps({"copy_calibration": {"bytes_read": nbytes, "bytes_written": nbytes, "dispatches": 3}}))
         return 0
 
-    if args.config in ("batch", "serve", "grad") and args.gpus == 1:
+    if args.config in ("batch", "serve", "grad", "layer_curve") and args.gpus == 1:
         import torch  # noqa: F401
-        res = {"batch": bench_batch, "serve": bench_serve, "grad": bench_grad}[args.config](args)
+        res = {"batch": bench_batch, "serve": bench_serve, "grad": bench_grad,
+               "layer_curve": bench_layer_curve}[args.config](args)
         print(json.dumps(res), flush=True)
         return 0
 
@@ -431,6 +575,32 @@ def main(argv=None):
               "single-device and no multi-GPU path exists", file=sys.stderr)
         return 2
 
+    from paper_2309_04841_amd import _lib
+    _lib.set_tuning(_lib.TUNE_WIDE_TILES, args.wide_tiles)
+    _lib.set_tuning(_lib.TUNE_FUSE_LAYERS, args.fuse_layers)
+    res = measure_eval(args.config, args.diag, args.steps, args.warmup,
+                       None if args.no_cpu_baseline else args.cpu_budget)
+    if res is None:
+        return 1
+    if args.config == "labs26" and not args.headline_only:
+        # the rest of the metric: the complex64 n=31 evaluation and the served mix
+        c2b = measure_eval("labs31", None, args.c2b_steps, 2, None if args.no_cpu_baseline else args.cpu_budget)
+        if c2b is None:
+            return 1
+        res["c2b"] = {k: c2b[k] for k in ("metric", "value", "unit", "ms_per_step", "dtype", "config", "roofline")
+                      if k in c2b}
+        if "cpu_baseline" in c2b:
+            res["c2b"]["cpu_baseline"] = c2b["cpu_baseline"]
+        res["serve"] = {name: serve_summary(name) for name in SERVE_MIXES}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def measure_eval(config, diag_name, steps, warmup, cpu_budget):
+    """One workload of CONFIGS: precompute (timed apart), `warmup` evaluations,
+    then `steps` evaluations timed with HIP events on the stream they run on.
+    Returns the result dict (roofline and, unless cpu_budget is None, the
+    oracle's sampled rate), or None if the objective is not reproducible."""
     import numpy as np
     import torch
 
@@ -438,11 +608,9 @@ def main(argv=None):
     from paper_2309_04841_amd import _lib
     import workloads as W
 
-    _lib.set_tuning(_lib.TUNE_WIDE_TILES, args.wide_tiles)
-    _lib.set_tuning(_lib.TUNE_FUSE_LAYERS, args.fuse_layers)
-    spec = dict(CONFIGS[args.config])
-    if args.diag:
-        spec["diag"] = args.diag
+    spec = dict(CONFIGS[config])
+    if diag_name:
+        spec["diag"] = diag_name
     cfg = getattr(W, spec["make"])()
     n, p = cfg["n"], cfg["p"]
     dev = torch.device("cuda:0")
@@ -480,7 +648,7 @@ def main(argv=None):
         def step():
             q.qaoa_evolve(n, gamma, beta, diag, psi, init=True, diag_offset=off, out=out, work=work)
 
-    for _ in range(max(1, args.warmup)):  # at least one evaluation, the reference for reproducibility
+    for _ in range(max(1, warmup)):  # at least one evaluation, the reference for reproducibility
         step()
     torch.cuda.synchronize()
     e_first = out.cpu().numpy().copy()
@@ -489,17 +657,17 @@ def main(argv=None):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record(stream)
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_total = start.elapsed_time(end)
-    ms_per_step = ms_total / args.steps
+    ms_per_step = ms_total / steps
     e_last = out.cpu().numpy()
     if not (np.isfinite(e_last).all() and np.array_equal(e_first, e_last)):
         print(f"bench.py: non-reproducible or non-finite objective {e_first} vs {e_last}", file=sys.stderr)
-        return 1
+        return None
 
     if mixer:
         plan = _lib.xy_plan_describe(n, mcode, _lib.state_dtype_code(psi))
@@ -518,13 +686,13 @@ def main(argv=None):
     achieved = (bytes_per_eval / launches) / (avg_launch_ms * 1e-3) / 1e9
 
     res = {
-        "metric": METRIC if args.config == "labs26" else
+        "metric": METRIC if config == "labs26" else
         f"QAOA expectation evals/s, LABS n={n} p={p}" + (f", {mixer} mixer" if mixer else ""),
-        "value": args.steps / (ms_total * 1e-3),
+        "value": steps / (ms_total * 1e-3),
         "unit": "evals/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": max(1, args.warmup),
+        "steps": steps,
+        "warmup": max(1, warmup),
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -536,8 +704,8 @@ def main(argv=None):
             "state": cfg["dtype"], "mixer": mixer or "x",
             "cost_vector": {"i32": "int32", "u16": "uint16", "f64": "float64"}[spec["diag"]],
             "schedule": "linear ramp, seeded", "sweeps_per_layer": len(plan["sweeps"]),
-            "tile_bits": plan["sweeps"][0]["tb"], "wide_tiles": args.wide_tiles, "fuse_layers": args.fuse_layers,
-            "launches_per_eval": launches,
+            "tile_bits": plan["sweeps"][0]["tb"], "wide_tiles": _lib.get_tuning(_lib.TUNE_WIDE_TILES),
+            "fuse_layers": _lib.get_tuning(_lib.TUNE_FUSE_LAYERS), "launches_per_eval": launches,
             "precompute_ms": precompute_ms, "E": float(e_last[0]), "norm": float(e_last[1]),
             "wall_s_timed": wall,
         },
@@ -554,12 +722,11 @@ def main(argv=None):
             "avg_launch_ms": avg_launch_ms,
         },
     }
-    if not args.no_cpu_baseline:
-        del psi, diag, work
-        torch.cuda.empty_cache()
-        res["cpu_baseline"] = cpu_baseline(cfg, args.cpu_budget, mixer)
-    print(json.dumps(res), flush=True)
-    return 0
+    del psi, diag, work
+    torch.cuda.empty_cache()
+    if cpu_budget is not None:
+        res["cpu_baseline"] = cpu_baseline(cfg, cpu_budget, mixer)
+    return res
 
 
 if __name__ == "__main__":

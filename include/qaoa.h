@@ -148,12 +148,14 @@ int qaoa_precompute_diag(int n, int64_t num_terms, const double *w, const int64_
  *
  * Phase factors: for F64 cost vectors exp(-i gamma_l c) is evaluated from the
  * double-precision angle gamma_l * c[x].  For integer cost vectors (I32 values in
- * [-2^15, 2^15), all U16 values) it is the product of two table entries
- * exp(-i gamma_l (256 m + base)) * exp(-i gamma_l j) with c = 256 m + j + base,
- * each evaluated in double precision (agreeing with the direct evaluation to a
- * few units in the last place of the angle); other I32 values use the direct
- * evaluation.  complex64 states are updated in double precision and rounded to
- * float when stored.  Results are deterministic (fixed reduction order).
+ * [-2^15, 2^15), all U16 values) it is the product of three table entries
+ * exp(-i gamma_l (256 m + base)) * exp(-i gamma_l 16 j) * exp(-i gamma_l k) with
+ * c = 256 m + 16 j + k + base, each evaluated in double precision from an
+ * exactly representable angle (agreeing with the direct evaluation to a few
+ * units in the last place of the angle); a workgroup holding other I32 values
+ * takes the same three-entry product twice, over the value's bytes.  complex64
+ * states are updated in double precision and rounded to float when stored.
+ * Results are deterministic (fixed reduction order).
  */
 int qaoa_evolve(int n, int p, const double *gamma, const double *beta,
                 const void *d_diag, int diag_dtype, double diag_offset, size_t diag_bytes,

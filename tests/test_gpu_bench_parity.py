@@ -1,0 +1,265 @@
+"""Oracle parity at the configurations the benchmark times, in its launch
+configuration (the library's default tuning: 2^14-element complex128 tiles and
+layer fusion), and at the sizes where the sweep plans change shape:
+
+* LABS n=26 p=10 complex128, uint16 (as benchmarked) and int32: the full state
+  and E against the oracle;
+* complex64 three-sweep plans (n >= 23): n = 23, 24 and 28, p = 3 and 4, uint16
+  and int32, element by element;
+* LABS n=31 p=10 complex64 uint16 (as benchmarked): the full cost vector, the
+  full state (streamed from the GPU in chunks) and E;
+* adjoint gradient, LABS n=24 p=20 complex128, uint16 and int32: all 40
+  components against the oracle's gradient;
+* seeded gradients at n = 21..23, whose reverse plans take three sweeps.
+
+Tolerances as in the other parity tests: complex128 ||dpsi||_2 <= 1e-10 and
+|dE| <= 1e-10 max(1, |E|); complex64 1e-5 for both; gradients
+1e-9 (complex128) or 1e-5 (complex64) times max(1, ||grad||_inf).
+"""
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TD = {"complex64": torch.complex64, "complex128": torch.complex128}
+_ORACLE = {}
+
+
+@pytest.fixture(scope="module")
+def q():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2309_04841_amd as q
+    return q
+
+
+@pytest.fixture(scope="module")
+def L(q):
+    from paper_2309_04841_amd import _lib
+    # the benchmark runs with the library defaults
+    assert _lib.get_tuning(_lib.TUNE_WIDE_TILES) == 1 and _lib.get_tuning(_lib.TUNE_FUSE_LAYERS) == 1
+    return _lib
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _state_error(psi_gpu, ref, chunk=1 << 24):
+    """(||psi_gpu - ref||_2, max |psi_gpu - ref|), reading the GPU state in chunks."""
+    sq, mx = 0.0, 0.0
+    for i in range(0, ref.size, chunk):
+        d = psi_gpu[i:i + chunk].cpu().numpy().astype(np.complex128) - ref[i:i + chunk]
+        sq += float(np.vdot(d, d).real)
+        mx = max(mx, float(np.abs(d).max()))
+    return float(np.sqrt(sq)), mx
+
+
+def _cost_equal(diag, off, c, chunk=1 << 24):
+    """Integer cost vector on the GPU (stored + offset) equals the oracle's, bit for bit."""
+    raw = diag.view(torch.int16) if diag.dtype == torch.uint16 else diag
+    for i in range(0, c.size, chunk):
+        v = raw[i:i + chunk].cpu().numpy().astype(np.int64)
+        if diag.dtype == torch.uint16:
+            v &= 0xFFFF
+        if not np.array_equal(v.astype(np.float64) + off, c[i:i + chunk]):
+            return False
+    return True
+
+
+def _oracle_labs(n, gamma, beta):
+    """(c, psi, E, norm) of LABS n from |+>^n, cached per (n, angles)."""
+    key = ("labs", n, tuple(gamma), tuple(beta))
+    if key not in _ORACLE:
+        _ORACLE.clear()
+        c = oracle.diag_labs(n).astype(np.float64)
+        ref = oracle.evolve(n, c, gamma, beta)
+        E, nrm = oracle.expectation(n, ref, c)
+        _ORACLE[key] = (c, ref, E, nrm)
+    return _ORACLE[key]
+
+
+@pytest.mark.parametrize("ddt", ["u16", "i32"])
+def test_labs26_p10_c128_as_benchmarked(q, L, ddt):
+    cfg = W.C2A()
+    n, g, b = cfg["n"], cfg["gamma"], cfg["beta"]
+    plan = L.plan_describe(n, L.QAOA_C128)
+    assert plan["wide"] and [(s["tb"], s["R"]) for s in plan["sweeps"]] == [(14, 10), (14, 2)]
+    sched = L.schedule_describe(n, len(g), L.QAOA_C128)
+    assert len(sched) == 11 and sum(1 for s in sched if s[2] & L.F_FUSE) == 9
+    _say(f"LABS n=26 p=10 c128 {ddt}: GPU")
+    diag, off = q.qaoa_precompute_diag(n, cfg["terms"], ddt, device="cuda")
+    psi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    q.qaoa_evolve(n, g, b, diag, psi, init=True, diag_offset=off, out=out)
+    torch.cuda.synchronize()
+    eo = out.cpu().numpy()
+    _say(f"LABS n=26 p=10 c128 {ddt}: oracle")
+    c, ref, E, nrm = _oracle_labs(n, g, b)
+    assert _cost_equal(diag, off, c)
+    err, mx = _state_error(psi, ref)
+    _say(f"  |dpsi|_2={err:.3e} max={mx:.3e} E gpu={eo[0]!r} oracle={E!r}")
+    assert err <= 1e-10
+    assert abs(eo[0] - E) <= 1e-10 * max(1.0, abs(E))
+    assert abs(eo[1] - nrm) <= 1e-10
+    del psi, diag
+    torch.cuda.empty_cache()
+
+
+C64_CASES = [(23, 3, "u16", "random"), (23, 4, "i32", "labs"), (24, 3, "i32", "random"),
+             (24, 4, "u16", "labs"), (28, 3, "u16", "labs"), (28, 3, "i32", "labs")]
+
+
+@pytest.mark.parametrize("n,p,ddt,problem", C64_CASES)
+def test_c64_three_sweep_plans(q, L, n, p, ddt, problem):
+    plan = L.plan_describe(n, L.QAOA_C64)
+    assert len(plan["sweeps"]) == 3 and not plan["single"]
+    if problem == "labs":
+        terms = W.labs_terms(n)
+        gamma, beta = W.linear_ramp(p, seed=n)
+    else:
+        terms = W.random_terms(n, 2 * n + 3, seed=700 + n, max_order=4, integer=True, wmax=5)
+        rng = np.random.default_rng(800 + n)
+        gamma, beta = rng.uniform(-1.5, 1.5, size=p), rng.uniform(-np.pi, np.pi, size=p)
+    _say(f"c64 three-sweep n={n} p={p} {ddt} {problem}: GPU")
+    diag, off = q.qaoa_precompute_diag(n, terms, ddt, device="cuda")
+    psi = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    q.qaoa_evolve(n, gamma, beta, diag, psi, init=True, diag_offset=off, out=out)
+    torch.cuda.synchronize()
+    eo = out.cpu().numpy()
+    _say(f"c64 three-sweep n={n} p={p} {ddt} {problem}: oracle")
+    if problem == "labs":
+        c, ref, E, nrm = _oracle_labs(n, gamma, beta)
+    else:
+        c = oracle.diag_terms(n, terms)
+        ref = oracle.evolve(n, c, gamma, beta)
+        E, nrm = oracle.expectation(n, ref, c)
+    assert _cost_equal(diag, off, c)
+    err, mx = _state_error(psi, ref)
+    _say(f"  |dpsi|_2={err:.3e} max={mx:.3e} E gpu={eo[0]!r} oracle={E!r}")
+    assert err <= 1e-5
+    assert abs(eo[0] - E) <= 1e-5 * max(1.0, abs(E))
+    assert abs(eo[1] - nrm) <= 1e-5
+    del psi, diag
+    torch.cuda.empty_cache()
+
+
+def _mem_available():
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemAvailable:"):
+                    return int(line.split()[1]) * 1024
+    except OSError:
+        pass
+    return os.sysconf("SC_PAGE_SIZE") * os.sysconf("SC_AVPHYS_PAGES")
+
+
+def test_labs31_p10_c64_as_benchmarked(q, L):
+    """The whole n=31 evaluation against the oracle.  The oracle holds a 32 GiB
+    complex128 state and a 16 GiB float64 cost vector (plus 16 GiB while the
+    integer LABS vector is converted), so it needs about 64 GiB of host memory;
+    with less available the test is skipped and says so."""
+    need = 64 << 30
+    avail = _mem_available()
+    if avail < need:
+        pytest.skip(f"the n=31 oracle needs about 64 GiB of host memory, {avail / 2**30:.0f} GiB available")
+    cfg = W.C2B()
+    n, g, b = cfg["n"], cfg["gamma"], cfg["beta"]
+    plan = L.plan_describe(n, L.QAOA_C64)
+    assert [(s["tb"], s["R"]) for s in plan["sweeps"]] == [(13, 10), (13, 4), (13, 4)]
+    assert len(L.schedule_describe(n, len(g), L.QAOA_C64)) == 21
+    _ORACLE.clear()
+    _say("LABS n=31 p=10 c64 u16: GPU")
+    diag, off = q.qaoa_precompute_diag(n, cfg["terms"], "u16", device="cuda")
+    psi = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    q.qaoa_evolve(n, g, b, diag, psi, init=True, diag_offset=off, out=out)
+    torch.cuda.synchronize()
+    eo = out.cpu().numpy()
+    t0 = time.perf_counter()
+    _say(f"LABS n=31 oracle: cost vector ({oracle.num_threads()} threads, "
+         f"{avail / 2**30:.0f} GiB host memory available)")
+    c = oracle.diag_labs(n)
+    c = c.astype(np.float64)
+    _say(f"  cost vector {time.perf_counter() - t0:.1f} s; comparing with the GPU's")
+    assert _cost_equal(diag, off, c)
+    del diag
+    ref = np.empty(1 << n, dtype=np.complex128)
+    for l in range(len(g)):
+        oracle.evolve_inplace(n, c, g[l:l + 1], b[l:l + 1], ref, init=(l == 0))
+        _say(f"  oracle layer {l + 1}/{len(g)} at {time.perf_counter() - t0:.1f} s")
+    E, nrm = oracle.expectation(n, ref, c)
+    del c
+    err, mx = _state_error(psi, ref)
+    _say(f"  |dpsi|_2={err:.3e} max={mx:.3e} E gpu={eo[0]!r} oracle={E!r} ({time.perf_counter() - t0:.1f} s)")
+    assert err <= 1e-5
+    assert abs(eo[0] - E) <= 1e-5 * max(1.0, abs(E))
+    assert abs(eo[1] - nrm) <= 1e-5
+    del psi, ref
+    torch.cuda.empty_cache()
+
+
+def _gpu_grad(q, n, terms, ddt, dtype, g, b):
+    diag, off = q.qaoa_precompute_diag(n, terms, ddt, device="cuda")
+    psi = torch.empty(1 << n, dtype=TD[dtype], device="cuda")
+    adj = torch.empty_like(psi)
+    out = q.qaoa_grad(n, g, b, diag, psi, adj, diag_offset=off).cpu().numpy()
+    del psi, adj, diag
+    p = len(g)
+    return out[0], out[1:1 + p], out[1 + p:]
+
+
+def _check_grad(got, want, tol):
+    E, dg, db = got
+    Er, dgr, dbr = want
+    scale = max(1.0, float(np.max(np.abs(np.concatenate([dgr, dbr])))))
+    _say(f"  E {E!r} / {Er!r}; max |d dgamma| {np.max(np.abs(dg - dgr)):.3e}, "
+         f"max |d dbeta| {np.max(np.abs(db - dbr)):.3e}, scale {scale:.3e}")
+    assert abs(E - Er) <= tol * max(1.0, abs(Er))
+    assert np.max(np.abs(dg - dgr)) <= tol * scale, (dg, dgr)
+    assert np.max(np.abs(db - dbr)) <= tol * scale, (db, dbr)
+
+
+@pytest.mark.parametrize("ddt", ["u16", "i32"])
+def test_c4_gradient_against_oracle(q, L, ddt):
+    cfg = W.C4()
+    n, g, b = cfg["n"], cfg["gamma"], cfg["beta"]
+    assert len(L.plan_describe(n, L.QAOA_C128, kind=L.PLAN_ADJOINT)["sweeps"]) == 3
+    _say(f"C4 gradient LABS n=24 p=20 c128 {ddt}: GPU")
+    got = _gpu_grad(q, n, cfg["terms"], ddt, "complex128", g, b)
+    key = ("grad", n, tuple(g), tuple(b))
+    if key not in _ORACLE:
+        _ORACLE.clear()
+        _say("C4 gradient: oracle")
+        _ORACLE[key] = oracle.grad(n, oracle.diag_labs(n).astype(np.float64), g, b)
+    _check_grad(got, _ORACLE[key], 1e-9)
+    torch.cuda.empty_cache()
+
+
+GRAD3_CASES = [(21, 3, "complex64", "u16"), (21, 2, "complex128", "i32"), (22, 3, "complex128", "u16"),
+               (22, 2, "complex64", "i32"), (23, 2, "complex128", "f64"), (23, 3, "complex64", "u16")]
+
+
+@pytest.mark.parametrize("n,p,dtype,ddt", GRAD3_CASES)
+def test_gradient_three_sweep_reverse_plans(q, L, n, p, dtype, ddt):
+    code = L.QAOA_C128 if dtype == "complex128" else L.QAOA_C64
+    assert len(L.plan_describe(n, code, kind=L.PLAN_ADJOINT)["sweeps"]) == 3
+    terms = W.random_terms(n, 2 * n + 3, seed=900 + n, max_order=4, integer=ddt != "f64", wmax=5)
+    rng = np.random.default_rng(950 + n)
+    g, b = rng.uniform(-0.5, 0.5, size=p), rng.uniform(-np.pi, np.pi, size=p)
+    _say(f"gradient n={n} p={p} {dtype} {ddt}: GPU")
+    got = _gpu_grad(q, n, terms, ddt, dtype, g, b)
+    _say(f"gradient n={n} p={p} {dtype} {ddt}: oracle")
+    want = oracle.grad(n, oracle.diag_terms(n, terms), g, b)
+    _check_grad(got, want, 1e-9 if dtype == "complex128" else 1e-5)
+    torch.cuda.empty_cache()

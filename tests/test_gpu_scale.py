@@ -1,9 +1,9 @@
-"""Full-size GPU checks in the launch configuration the benchmark times.
-
-LABS n=26 complex128 and n=31 complex64, p=10, linear-ramp schedule.  At these
-sizes the oracle cannot evolve the state in seconds, so the checks are
-  * cost vector at sampled basis states against the oracle's direct LABS sum;
-  * a full element-by-element oracle comparison at n=26 for p=1;
+"""Full-size GPU checks at the benchmark's sizes that complement the element-wise
+oracle comparisons of the benchmarked evaluations (LABS n=26 p=10 complex128 and
+n=31 p=10 complex64, in test_gpu_bench_parity.py):
+  * cost vector at sampled basis states against the oracle's direct LABS sum,
+    including n=33 (indices above 2^32);
+  * a full element-by-element oracle comparison at n=26 for p=1 (unfused plan);
   * properties that hold at any size: norm conservation, beta=0 gives the mean
     of c (= n(n-1)/2 for LABS), gamma=0 gives exp(-i n sum beta)|+>,
     E(-gamma, -beta) = E(gamma, beta), LABS E(gamma_l + pi) = E,
