@@ -529,6 +529,11 @@ def bench_layer_curve(args):
             "higher_is_better": False, "n_gpus": 1, "data": "synthetic", "rows": rows}
 
 
+def _progress(msg):
+    """One line per finished part of the run, on stderr (stdout holds the JSON line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -582,16 +587,21 @@ def main(argv=None):
                        None if args.no_cpu_baseline else args.cpu_budget)
     if res is None:
         return 1
+    _progress(f"{args.config}: {res['value']:.2f} {res['unit']}")
     if args.config == "labs26" and not args.headline_only:
         # the rest of the metric: the complex64 n=31 evaluation and the served mix
         c2b = measure_eval("labs31", None, args.c2b_steps, 2, None if args.no_cpu_baseline else args.cpu_budget)
         if c2b is None:
             return 1
+        _progress(f"labs31: {c2b['value']:.3f} {c2b['unit']}")
         res["c2b"] = {k: c2b[k] for k in ("metric", "value", "unit", "ms_per_step", "dtype", "config", "roofline")
                       if k in c2b}
         if "cpu_baseline" in c2b:
             res["c2b"]["cpu_baseline"] = c2b["cpu_baseline"]
-        res["serve"] = {name: serve_summary(name) for name in SERVE_MIXES}
+        res["serve"] = {}
+        for name in SERVE_MIXES:
+            res["serve"][name] = serve_summary(name)
+            _progress(f"serve {name}: {res['serve'][name]['capacity_requests_per_s']:.1f} requests/s capacity")
     print(json.dumps(res), flush=True)
     return 0
 

@@ -42,7 +42,8 @@ def _problems(ns):
         if i % 2 == 0:
             probs.append((n, W.labs_terms(n)))
         else:
-            probs.append((n, W.maxcut_terms(W.random_regular_graph(3, n, seed=n))))
+            d = 3 if n % 2 == 0 else 4  # a d-regular graph on n vertices needs d n even
+            probs.append((n, W.maxcut_terms(W.random_regular_graph(d, n, seed=n))))
     return probs
 
 
