@@ -169,6 +169,27 @@ int qaoa_evolve(int n, int p, const double *gamma, const double *beta,
                 double *d_out, void *d_work, size_t work_bytes, void *stream);
 
 /*
+ * qaoa_evolve_noalloc -- qaoa_evolve for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same arguments without the workspace, the same kernels
+ * and results (bitwise equal to qaoa_evolve with a workspace).  Its scratch is
+ * a static device array of QAOA_NOALLOC_SCRATCH_BYTES per GPU, held until the
+ * process ends; it covers complex64 states up to n = 32 and complex128 states
+ * up to n = 31 (any p).  Larger requests return QAOA_ERR_NOMEM without
+ * enqueuing anything.  The call itself allocates nothing: the array's device
+ * address is looked up once per device (the stream's device, or the current
+ * device for the null stream) and reused.  All calls on one GPU share that
+ * array and it keeps the last call's contents: calls that overlap on one GPU
+ * (different streams or host threads without ordering) race and give wrong
+ * results; calls ordered on one stream are safe.
+ */
+#define QAOA_NOALLOC_SCRATCH_BYTES ((size_t)9 << 20)
+int qaoa_evolve_noalloc(int n, int p, const double *gamma, const double *beta,
+                        const void *d_diag, int diag_dtype, double diag_offset, size_t diag_bytes,
+                        void *d_state, int state_dtype, size_t state_bytes, int init,
+                        double *d_out, void *stream);
+
+/*
  * qaoa_expectation -- E = sum_x |psi_x|^2 c_x and sum_x |psi_x|^2 (Section 3.1),
  * accumulated in FP64 with a fixed reduction order.  Any cost vector of the
  * right length may be passed (it need not be the one used for evolution).

@@ -6,11 +6,11 @@ transverse-field mixer applied by hand-written HIP kernels, and the objective
 E = sum |psi|^2 c reduced in FP64.  The kernels sit behind the C ABI in
 include/qaoa.h (libqaoa.so); this package is its thin Python binding.
 """
-from ._lib import (QaoaError, qaoa_evolve, qaoa_evolve_batch, qaoa_evolve_xy, qaoa_expectation, qaoa_grad,
+from ._lib import (QaoaError, qaoa_evolve, qaoa_evolve_batch, qaoa_evolve_noalloc, qaoa_evolve_xy, qaoa_expectation, qaoa_grad,
                    qaoa_precompute_diag, version, workspace_bytes)
 from .autograd import QAOAObjective, qaoa_objective
 from .server import QAOAServer
 from .simulator import Simulator
 
-__all__ = ["Simulator", "QAOAServer", "QaoaError", "qaoa_precompute_diag", "qaoa_evolve", "qaoa_evolve_batch", "qaoa_evolve_xy",
+__all__ = ["Simulator", "QAOAServer", "QaoaError", "qaoa_precompute_diag", "qaoa_evolve", "qaoa_evolve_batch", "qaoa_evolve_noalloc", "qaoa_evolve_xy",
            "qaoa_expectation", "qaoa_grad", "qaoa_objective", "QAOAObjective", "workspace_bytes", "version"]

@@ -19,6 +19,7 @@ QAOA_C64, QAOA_C128 = 0, 1
 QAOA_DIAG_F64, QAOA_DIAG_I32, QAOA_DIAG_U16 = 0, 1, 2
 QAOA_OP_PRECOMPUTE, QAOA_OP_EVOLVE, QAOA_OP_EXPECTATION, QAOA_OP_GRAD = range(4)
 QAOA_MAX_QUBITS = 34
+QAOA_NOALLOC_SCRATCH_BYTES = 9 << 20
 
 EXPORTS = ("qaoa_version", "qaoa_last_error", "qaoa_workspace_bytes", "qaoa_precompute_diag",
            "qaoa_evolve", "qaoa_expectation", "qaoa_grad", "qaoa_plan_describe", "qaoa_evolve_batch",
@@ -26,7 +27,7 @@ EXPORTS = ("qaoa_version", "qaoa_last_error", "qaoa_workspace_bytes", "qaoa_prec
            "qaoa_server_destroy", "qaoa_server_add_problem", "qaoa_server_submit", "qaoa_server_wait",
            "qaoa_server_stats_get", "qaoa_server_reset_stats", "qaoa_schedule_describe", "qaoa_set_tuning",
            "qaoa_get_tuning", "qaoa_evolve_xy", "qaoa_xy_workspace_bytes", "qaoa_xy_plan_describe",
-           "qaoa_layout_describe")
+           "qaoa_evolve_noalloc", "qaoa_layout_describe")
 
 _STATUS_NAMES = {0: "QAOA_OK", 1: "QAOA_ERR_INVALID", 2: "QAOA_ERR_RANGE", 3: "QAOA_ERR_NOMEM",
                  4: "QAOA_ERR_DEVICE", 5: "QAOA_ERR_UNSUPPORTED"}
@@ -54,6 +55,8 @@ def _load() -> ctypes.CDLL:
     lib.qaoa_precompute_diag.argtypes = [I, I64, P, P, P, I, P, SZ, ctypes.POINTER(D), P, SZ, P]
     lib.qaoa_evolve.restype = I
     lib.qaoa_evolve.argtypes = [I, I, P, P, P, I, D, SZ, P, I, SZ, I, P, P, SZ, P]
+    lib.qaoa_evolve_noalloc.restype = I
+    lib.qaoa_evolve_noalloc.argtypes = [I, I, P, P, P, I, D, SZ, P, I, SZ, I, P, P]
     lib.qaoa_expectation.restype = I
     lib.qaoa_expectation.argtypes = [I, P, I, SZ, P, I, D, SZ, P, P, SZ, P]
     lib.qaoa_grad.restype = I
@@ -309,6 +312,20 @@ def qaoa_evolve(n: int, gamma, beta, diag: torch.Tensor, state: torch.Tensor, in
     check(lib.qaoa_evolve(n, p, _f64(gamma), _f64(beta), _dev_ptr(diag), ddt, float(diag_offset), _nbytes(diag),
                           _dev_ptr(state), sdt, _nbytes(state), 1 if init else 0, _dev_ptr(out),
                           _dev_ptr(work), 0 if work is None else _nbytes(work), _stream(state.device)))
+
+
+def qaoa_evolve_noalloc(n: int, gamma, beta, diag: torch.Tensor, state: torch.Tensor, init: bool = True,
+                        diag_offset: float = 0.0, out: torch.Tensor | None = None) -> None:
+    """qaoa_evolve without a workspace: the library's static per-GPU scratch
+    serves instead (complex64 up to n=32, complex128 up to n=31); calls that
+    overlap on one GPU race."""
+    p = len(gamma)
+    if len(beta) != p:
+        raise ValueError("gamma and beta differ in length")
+    sdt, ddt = state_dtype_code(state), diag_dtype_code(diag)
+    check(lib.qaoa_evolve_noalloc(n, p, _f64(gamma), _f64(beta), _dev_ptr(diag), ddt, float(diag_offset),
+                                  _nbytes(diag), _dev_ptr(state), sdt, _nbytes(state), 1 if init else 0,
+                                  _dev_ptr(out), _stream(state.device)))
 
 
 def qaoa_expectation(n: int, state: torch.Tensor, diag: torch.Tensor, diag_offset: float = 0.0,

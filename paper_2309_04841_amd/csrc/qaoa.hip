@@ -1349,6 +1349,75 @@ int qaoa_evolve(int n, int p, const double* gamma, const double* beta, const voi
                         init, d_out, 1, d_work, tuning_now(), st, d_alt);
 }
 
+}  // extern "C"
+
+// Scratch of qaoa_evolve_noalloc: the evolve workspace (per-workgroup (E, norm)
+// partials, parameter rows, phase tables) in a static device array, so that
+// callers that cannot allocate need no workspace.  Each GPU holds its own copy
+// for the life of the process.  In host code this name is only a handle for
+// hipGetSymbolAddress: kernels receive the device address looked up per device.
+static __device__ __align__(256) unsigned char noalloc_scratch[QAOA_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices];  // device address of noalloc_scratch, per device (null until looked up)
+
+// Device address of noalloc_scratch on device `dev`, looked up on first use
+// with that device current and kept for later calls.
+int noalloc_scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(QAOA_ERR_DEVICE, "device %d outside [0, %d)", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != dev) HIP_TRY(hipSetDevice(dev));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(noalloc_scratch));
+    if (cur != dev) HIP_TRY(hipSetDevice(cur));
+    if (e != hipSuccess || ptr == nullptr)
+      return fail(QAOA_ERR_DEVICE, "hipGetSymbolAddress(noalloc_scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return QAOA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qaoa_evolve_noalloc(int n, int p, const double* gamma, const double* beta, const void* d_diag, int diag_dtype,
+                        double diag_offset, size_t diag_bytes, void* d_state, int state_dtype, size_t state_bytes,
+                        int init, double* d_out, void* stream) {
+  int rc = validate_common(n, d_diag, diag_dtype, diag_offset, diag_bytes, d_state, state_dtype, state_bytes);
+  if (rc) return rc;
+  rc = validate_angles(p, gamma, beta);
+  if (rc) return rc;
+  if (init != 0 && init != 1) return fail(QAOA_ERR_INVALID, "init must be 0 or 1");
+  const size_t need = (p > 0 || d_out) ? evolve_work_bytes(n, state_dtype) : 0;
+  if (need > (size_t)QAOA_NOALLOC_SCRATCH_BYTES)
+    return fail(QAOA_ERR_NOMEM,
+                "qaoa_evolve_noalloc: n=%d %s needs %zu bytes of scratch, more than its static %zu bytes "
+                "(use qaoa_evolve with a workspace)",
+                n, state_dtype == QAOA_C128 ? "complex128" : "complex64", need, (size_t)QAOA_NOALLOC_SCRATCH_BYTES);
+  void* work = nullptr;
+  if (need) {
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    int dev = -1;
+    if (st) {
+      HIP_TRY(hipStreamGetDevice(st, &dev));
+    } else {
+      HIP_TRY(hipGetDevice(&dev));
+    }
+    rc = noalloc_scratch_address(dev, &work);
+    if (rc) return rc;
+  }
+  return qaoa_evolve(n, p, gamma, beta, d_diag, diag_dtype, diag_offset, diag_bytes, d_state, state_dtype,
+                     state_bytes, init, d_out, work, need ? (size_t)QAOA_NOALLOC_SCRATCH_BYTES : 0, stream);
+}
+
 int qaoa_expectation(int n, const void* d_state, int state_dtype, size_t state_bytes, const void* d_diag,
                      int diag_dtype, double diag_offset, size_t diag_bytes, double* d_out, void* d_work,
                      size_t work_bytes, void* stream) {

@@ -102,6 +102,26 @@ def test_evolve_rejects(kw, code):
     assert _lib.lib.qaoa_last_error() != b""
 
 
+def _evolve_noalloc(n=10, p=1, sdt=1, out=FAKE, init=1, off=0.0):
+    N = 1 << n
+    g = (ctypes.c_double * max(1, p))(*([0.1] * max(1, p)))
+    return _lib.lib.qaoa_evolve_noalloc(n, p, g, g, FAKE, 1, off, 4 * N, FAKE, sdt, (16 if sdt else 8) * N, init,
+                                        out, None)
+
+
+def test_evolve_noalloc_limits():
+    """The static scratch covers complex64 up to n=32 and complex128 up to n=31;
+    beyond that (and for invalid arguments) the call fails before touching the GPU."""
+    for sdt, nmax in ((_lib.QAOA_C64, 32), (_lib.QAOA_C128, 31)):
+        assert _lib.workspace_bytes(_lib.QAOA_OP_EVOLVE, nmax, sdt) <= _lib.QAOA_NOALLOC_SCRATCH_BYTES
+        assert _lib.workspace_bytes(_lib.QAOA_OP_EVOLVE, nmax + 1, sdt) > _lib.QAOA_NOALLOC_SCRATCH_BYTES
+        assert _evolve_noalloc(n=nmax + 1, sdt=sdt) == _lib.QAOA_ERR_NOMEM
+        assert b"static" in _lib.lib.qaoa_last_error()
+    assert _evolve_noalloc(init=3) == _lib.QAOA_ERR_INVALID
+    assert _evolve_noalloc(off=0.5) == _lib.QAOA_ERR_INVALID
+    assert _evolve_noalloc(p=-1) == _lib.QAOA_ERR_INVALID
+
+
 def _precompute(n=6, w=(1.0,), ptr=(0, 2), idx=(0, 1), ddt=1, diag=FAKE, dbytes=None, work=None, wbytes=0,
                 offset=True):
     N = 1 << n if 0 < n < 40 else 0
