@@ -143,14 +143,8 @@ int qaoa_precompute_diag(int n, int64_t num_terms, const double *w, const int64_
  *               0: start from the contents of d_state
  *   d_out       device, nullable: receives d_out[0] = E = sum |psi|^2 c and
  *               d_out[1] = sum |psi|^2 of the final state (FP64, no renormalisation)
- *   d_work      device workspace of qaoa_workspace_bytes(QAOA_OP_EVOLVE, ...) bytes
- *               (may be NULL only when p == 0 and d_out == NULL).  For plans with a
- *               sweep whose contiguous run is shorter than 128 bytes (complex128 at
- *               n = 26) that size includes a second state buffer, which lets that
- *               sweep write whole cache lines (see qaoa_layout_describe); a
- *               workspace of only the part before it (the size qaoa_evolve reports
- *               when it fails with QAOA_ERR_NOMEM) is accepted and runs every
- *               sweep in place, with bitwise the same results.
+ *   d_work      device workspace, >= qaoa_workspace_bytes(QAOA_OP_EVOLVE, ...) bytes
+ *               (may be NULL only when p == 0 and d_out == NULL)
  *
  * Phase factors: for F64 cost vectors exp(-i gamma_l c) is evaluated from the
  * double-precision angle gamma_l * c[x].  For integer cost vectors (I32 values in
@@ -367,25 +361,6 @@ int qaoa_plan_describe(int kind, int n, int state_dtype, int elem_bytes, int *ou
  * one tile and a single launch runs the layers), or -QAOA_ERR_INVALID.
  */
 int qaoa_schedule_describe(int kind, int n, int p, int state_dtype, int init, int reduce, int *out, int cap);
-
-/*
- * qaoa_layout_describe -- diagnostic: the state layout and buffer each launch
- * of the kind-0 schedule (same arguments as qaoa_schedule_describe) reads and
- * writes, for a call whose workspace holds a second state buffer (alt = 1) or
- * not (alt = 0).  Layouts are bit orders of the element positions in a state
- * buffer.  With a second buffer, a sweep whose contiguous run is shorter than
- * 128 bytes reads the caller's state in natural order (position = index) and
- * writes a rotated order, in which its segment-A bits follow the run, into the
- * second buffer, so its stores cover whole 128-byte lines; the next launch
- * reads that order there and writes the natural order back into the caller's
- * state.  Every other launch works in place in natural order.  Writes ten ints
- * per launch: the load layout (R, hA, qA, qB) and 1 if it is read from the
- * second buffer, then the same for the store: tile bits [0,R) sit at position
- * bits [0,R), [R,R+hA) at [qA,qA+hA), the rest from qB on, and the
- * block-index bits fill the other position bits in increasing order.  Returns
- * the number of ints needed, or -QAOA_ERR_INVALID.
- */
-int qaoa_layout_describe(int n, int p, int state_dtype, int init, int reduce, int alt, int *out, int cap);
 
 #ifdef __cplusplus
 }

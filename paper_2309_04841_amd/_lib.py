@@ -27,7 +27,7 @@ EXPORTS = ("qaoa_version", "qaoa_last_error", "qaoa_workspace_bytes", "qaoa_prec
            "qaoa_server_destroy", "qaoa_server_add_problem", "qaoa_server_submit", "qaoa_server_wait",
            "qaoa_server_stats_get", "qaoa_server_reset_stats", "qaoa_schedule_describe", "qaoa_set_tuning",
            "qaoa_get_tuning", "qaoa_evolve_xy", "qaoa_xy_workspace_bytes", "qaoa_xy_plan_describe",
-           "qaoa_evolve_noalloc", "qaoa_layout_describe")
+           "qaoa_evolve_noalloc")
 
 _STATUS_NAMES = {0: "QAOA_OK", 1: "QAOA_ERR_INVALID", 2: "QAOA_ERR_RANGE", 3: "QAOA_ERR_NOMEM",
                  4: "QAOA_ERR_DEVICE", 5: "QAOA_ERR_UNSUPPORTED"}
@@ -69,8 +69,6 @@ def _load() -> ctypes.CDLL:
     lib.qaoa_get_tuning.argtypes = [I, ctypes.POINTER(I)]
     lib.qaoa_schedule_describe.restype = I
     lib.qaoa_schedule_describe.argtypes = [I, I, I, I, I, I, P, I]
-    lib.qaoa_layout_describe.restype = I
-    lib.qaoa_layout_describe.argtypes = [I, I, I, I, I, I, P, I]
     lib.qaoa_grad_workspace_bytes.restype = I
     lib.qaoa_grad_workspace_bytes.argtypes = [I, I, I, I, ctypes.POINTER(SZ)]
     lib.qaoa_evolve_batch.restype = I
@@ -246,19 +244,6 @@ def schedule_describe(n: int, p: int, state_dtype: int = QAOA_C128, init: bool =
     lib.qaoa_schedule_describe(kind, n, p, state_dtype, int(init), int(reduce), buf, need)
     v = list(buf)[:need]
     return [tuple(v[i:i + 3]) for i in range(0, need, 3)]
-
-
-def layout_describe(n: int, p: int, state_dtype: int = QAOA_C128, init: bool = True, reduce: bool = True,
-                    alt: bool = True) -> list:
-    """State layouts and buffers of each launch of the evolve schedule (alt: the
-    workspace holds a second state buffer): [((R, hA, qA, qB), alt_read, (R, hA, qA, qB), alt_written)]."""
-    need = lib.qaoa_layout_describe(n, p, state_dtype, int(init), int(reduce), int(alt), None, 0)
-    if need < 0:
-        check(-need)
-    buf = (ctypes.c_int * max(need, 1))()
-    lib.qaoa_layout_describe(n, p, state_dtype, int(init), int(reduce), int(alt), buf, need)
-    v = list(buf)[:need]
-    return [(tuple(v[i:i + 4]), bool(v[i + 4]), tuple(v[i + 5:i + 9]), bool(v[i + 9])) for i in range(0, need, 10)]
 
 
 def workspace_bytes(op: int, n: int, state_dtype: int = QAOA_C128, diag_dtype: int = QAOA_DIAG_I32) -> int:

@@ -291,8 +291,7 @@ __device__ __forceinline__ void block_sum2(double& x, double& y, double* scratch
 // fused QAOA sweep
 // ----------------------------------------------------------------------------
 struct SweepArgs {
-  void* psi;          // state read by the launch (and written, unless psi_out differs)
-  void* psi_out;      // state written by the launch (sweeps; psi for in-place launches)
+  void* psi;
   const void* diag;
   const double2* ptab; // phase tables (integer cost vectors), kTabRow per layer
   double* partials;   // 2 doubles per block (E, norm) when F_EXPV
@@ -311,12 +310,6 @@ struct SweepArgs {
   int layer0;
   uint64_t set_stride_bytes;
   uint64_t partials_stride;
-  // Layouts of the state this launch reads and writes (the natural layout of g
-  // unless the host plans a rotated one between two launches), and the
-  // per-register position parts of the load window (tb - EB) and of the store
-  // window under them.  Cost values are always read in the natural layout.
-  Layout ld, st;
-  uint64_t goff_ld[16], goff_st[16];
 };
 
 struct LayerParams {
@@ -659,8 +652,7 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
   typename S::L* lds = reinterpret_cast<typename S::L*>(smem_raw);
   double2* tab = reinterpret_cast<double2*>(smem_raw + (1u << a.g.tb) * S::kLdsBytes);
   const uint32_t tid = threadIdx.x;
-  const uint32_t vb = xcd_block(blockIdx.x, gridDim.x);
-  const uint64_t base = block_base(vb, a.g);
+  const uint64_t base = block_base(xcd_block(blockIdx.x, gridDim.x), a.g);
   const uint32_t set = blockIdx.y;
   void* psi = reinterpret_cast<char*>(a.psi) + (uint64_t)set * a.set_stride_bytes;
   const LayerParams lp = layer_params(a, set, 0);
@@ -679,13 +671,15 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
   // they are read up front in the mapping the phase is applied in (the last
   // window of the chunk order).
   typename D::RawT cv[(EXPV || FUSE) ? E : 1];
-  if constexpr (INIT) {
+  {
+    const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g);
+    if constexpr (INIT) {
 #pragma unroll
-    for (int k = 0; k < E; ++k) { vr[k] = a.amp0; vi[k] = 0.0; }
-  } else {
-    const uint64_t xb = block_base_l(vb, a.g.tb, a.ld) + tile_off_l(thr_part<EB>(tid, w), a.ld);
+      for (int k = 0; k < E; ++k) { vr[k] = a.amp0; vi[k] = 0.0; }
+    } else {
 #pragma unroll
-    for (int k = 0; k < E; ++k) S::load(psi, xb + a.goff_ld[k], vr[k], vi[k]);
+      for (int k = 0; k < E; ++k) S::load(psi, xb + a.g.goff[w][k], vr[k], vi[k]);
+    }
   }
   if constexpr (EXPV) load_cost<D, EB>(cv, a, base, tid, w_load);
   // complex64 tiles hold the cost values from the start (their loads overlap
@@ -746,10 +740,9 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
     }
   }
   {
-    void* psi_o = reinterpret_cast<char*>(a.psi_out) + (uint64_t)set * a.set_stride_bytes;
-    const uint64_t xb = block_base_l(vb, a.g.tb, a.st) + tile_off_l(thr_part<EB>(tid, w), a.st);
+    const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g);
 #pragma unroll
-    for (int k = 0; k < E; ++k) S::store(psi_o, xb + a.goff_st[k], vr[k], vi[k]);
+    for (int k = 0; k < E; ++k) S::store(psi, xb + a.g.goff[w][k], vr[k], vi[k]);
   }
   if constexpr (EXPV) {
     __syncthreads();  // the tile buffer becomes reduction scratch (the last window change may have been wave-local)

@@ -264,137 +264,6 @@ std::vector<SweepStep> sweep_schedule(int nsw, int p, bool init, bool expv, bool
   return out;
 }
 
-// ---------------------------------------------------------------------------
-// State layouts between launches.  A sweep whose contiguous run is shorter
-// than a 128-byte line (2^14-element complex128 tiles at n = 26 keep two run
-// bits: 64-byte runs) writes every line in halves from two workgroups;
-// measured, those partial-line stores cost the launch far more than the
-// matching partial-line loads.  Such a sweep therefore writes a rotated layout,
-// in which its segment-A bits sit right above the run (global bits
-// [qA, qA + hA) at positions [R, R + hA), global bits [R, qA) moved up by hA),
-// so each of its store instructions writes whole lines.  The next launch
-// reads that layout (its loads get the short runs instead), and the last
-// launch of an evaluation always writes the natural layout.
-// ---------------------------------------------------------------------------
-using BitMap = std::vector<int>;  // position bit of each global bit
-
-BitMap identity_bits(int n) {
-  BitMap m(n);
-  for (int i = 0; i < n; ++i) m[i] = i;
-  return m;
-}
-
-// Global bit of each tile bit of g, and of each block-index bit (the gaps, in
-// increasing order).
-std::vector<int> tile_bits_of(const qk::TileGeom& g) {
-  std::vector<int> t;
-  for (int j = 0; j < g.R; ++j) t.push_back(j);
-  for (int j = 0; j < g.hA; ++j) t.push_back(g.qA + j);
-  for (int j = 0; j < g.tb - g.R - g.hA; ++j) t.push_back(g.qB + j);
-  return t;
-}
-std::vector<int> block_bits_of(int n, const qk::TileGeom& g) {
-  std::vector<bool> in(n, false);
-  for (int b : tile_bits_of(g)) in[b] = true;
-  std::vector<int> out;
-  for (int i = 0; i < n; ++i)
-    if (!in[i]) out.push_back(i);
-  return out;
-}
-
-bool short_run(const qk::TileGeom& g, size_t elem_bytes) { return ((size_t)1 << g.R) * elem_bytes < 128; }
-
-// The layout a short-run sweep g writes (see above).
-BitMap rotated_bits(int n, const qk::TileGeom& g) {
-  BitMap m = identity_bits(n);
-  for (int i = g.R; i < g.qA; ++i) m[i] = i + g.hA;
-  for (int i = g.qA; i < g.qA + g.hA; ++i) m[i] = i - g.qA + g.R;
-  return m;
-}
-
-// g's tiles under position map m in the kernels' Layout form, if there is one:
-// tile bits [0, R) at positions [0, R), the other tile bits in at most two runs
-// of consecutive positions, and the block-index bits, in their natural order,
-// at the remaining positions in increasing order (as block_base_l fills them).
-bool layout_under(int n, const qk::TileGeom& g, const BitMap& m, qk::Layout* out) {
-  const std::vector<int> tbits = tile_bits_of(g);
-  std::vector<int> pos;
-  for (int b : tbits) pos.push_back(m[b]);
-  const int tb = g.tb;
-  int R = 0;
-  while (R < tb && pos[R] == R) ++R;
-  int hA = 0;
-  const int qA = R < tb ? pos[R] : R;
-  while (R + hA < tb && pos[R + hA] == qA + hA) ++hA;
-  const int qB = R + hA < tb ? pos[R + hA] : qA + hA;
-  for (int j = R + hA; j < tb; ++j)
-    if (pos[j] != qB + (j - R - hA)) return false;
-  if (qA < R || qB < qA + hA || qB + (tb - R - hA) > n) return false;
-  std::vector<bool> used(n, false);
-  for (int q : pos) used[q] = true;
-  std::vector<int> gaps;
-  for (int i = 0; i < n; ++i)
-    if (!used[i]) gaps.push_back(i);
-  const std::vector<int> bbits = block_bits_of(n, g);
-  if (gaps.size() != bbits.size()) return false;
-  for (size_t i = 0; i < gaps.size(); ++i)
-    if (m[bbits[i]] != gaps[i]) return false;
-  *out = qk::Layout{R, hA, qA, qB};
-  return true;
-}
-
-// Load and store layouts of each launch of a schedule, and the buffers they
-// use.  A launch that reads one layout and writes another cannot work in
-// place (a workgroup would overwrite positions another has not read yet), so a
-// rotation goes out of place: the short-run sweep reads the caller's state in
-// natural order and writes the rotated order into a second state buffer (alt),
-// and the next launch reads it there and writes the natural order back into
-// the caller's buffer.  Every other launch works in place in natural order.
-// Without a second buffer (allow_alt false) every launch is in place.
-struct LaunchLayouts {
-  qk::Layout ld, st;
-  bool ld_alt, st_alt;  // read from / write to the second buffer
-};
-std::vector<LaunchLayouts> plan_layouts(int n, const Plan& pl, const std::vector<SweepStep>& sched, size_t elem_bytes,
-                                        bool allow_alt) {
-  std::vector<LaunchLayouts> out(sched.size());
-  for (size_t i = 0; i < sched.size(); ++i) {
-    const qk::TileGeom& g = pl.sweeps[sched[i].sweep];
-    out[i].ld = out[i].st = qk::natural_layout(g);
-    out[i].ld_alt = out[i].st_alt = false;
-  }
-  if (!allow_alt) return out;
-  for (size_t i = 0; i + 1 < sched.size(); ++i) {
-    const qk::TileGeom& g = pl.sweeps[sched[i].sweep];
-    if (!short_run(g, elem_bytes) || g.hA == 0 || g.qA <= g.R) continue;
-    const BitMap m = rotated_bits(n, g);
-    qk::Layout mine, next;
-    if (!layout_under(n, g, m, &mine) || !layout_under(n, pl.sweeps[sched[i + 1].sweep], m, &next)) continue;
-    out[i].st = mine;
-    out[i].st_alt = true;
-    out[i + 1].ld = next;
-    out[i + 1].ld_alt = true;
-    ++i;  // the reading launch writes the natural order back and does not rotate itself
-  }
-  return out;
-}
-
-// Whether some schedule of n qubits (either tile plan) would use the second
-// buffer: the evolve workspace then has room for one more state.
-bool uses_alt_buffer(int n, int state_dtype) {
-  const size_t S = state_dtype == QAOA_C128 ? 16 : 8;
-  for (bool wide : {false, true}) {
-    const Plan pl = state_plan(n, state_dtype, wide);
-    if (pl.single) continue;
-    for (bool fuse : {false, true}) {
-      const std::vector<SweepStep> sched = sweep_schedule((int)pl.sweeps.size(), 3, true, true, fuse);
-      for (const auto& l : plan_layouts(n, pl, sched, S, true))
-        if (l.st_alt) return true;
-    }
-  }
-  return false;
-}
-
 // Reverse (adjoint) sweeps hold two states per thread: 8 elements of each.
 constexpr int kEBAdj = 3;
 Plan adjoint_plan(int n, size_t state_bytes) { return make_plan(n, state_bytes, kEBAdj); }
@@ -596,17 +465,8 @@ template <class S, class D, bool INIT, bool PHASE, bool EXPV, bool FUSE = false,
 void launch_sweep_f(const qk::SweepArgs& a, uint64_t blocks, uint32_t sets, hipStream_t st) {
   const uint32_t threads = 1u << (a.g.tb - kEB);
   const size_t lds = tile_lds_bytes<S, D>(a.g, threads, PHASE || FUSE);
-  qk::SweepArgs b = with_offsets<S>(a, kEB);
-  // the state is loaded in the coalesced window; a fused or reducing sweep
-  // stores from it too (its reverse chunk order ends there), others from w_store
-  const int w_load = a.g.tb - kEB;
-  const int w_out = (EXPV || FUSE) ? w_load : a.g.w_store;
-  for (int k = 0; k < 16; ++k) {
-    b.goff_ld[k] = k < (1 << kEB) ? qk::tile_off_l((uint32_t)k << w_load, b.ld) : 0;
-    b.goff_st[k] = k < (1 << kEB) ? qk::tile_off_l((uint32_t)k << w_out, b.st) : 0;
-  }
   hipLaunchKernelGGL((qk::qaoa_sweep_kernel<S, D, kEB, INIT, PHASE, EXPV, FUSE, PLO, PHI>),
-                     dim3((uint32_t)blocks, sets), dim3(threads), lds, st, b);
+                     dim3((uint32_t)blocks, sets), dim3(threads), lds, st, with_offsets<S>(a, kEB));
 }
 
 // Sweeps specialise a short last chunk (register bits [1, 4), [2, 4) or
@@ -934,17 +794,6 @@ int enqueue_reduce(const double* partials, uint64_t count, uint64_t stride, uint
   return QAOA_OK;
 }
 size_t evolve_work_bytes(int n, int state_dtype) { return evolve_work(n, 1, qk::kPrepRows, state_dtype).total; }
-// The evolve workspace may also hold a second state buffer (see plan_layouts),
-// 256-byte aligned after the base part; it is only used when the caller's
-// workspace has room for it.
-size_t alt_offset(int n, int state_dtype) { return (evolve_work_bytes(n, state_dtype) + 255) / 256 * 256; }
-size_t alt_bytes(int n, int state_dtype) {
-  return uses_alt_buffer(n, state_dtype) ? ((size_t)1 << n) * (state_dtype == QAOA_C128 ? 16 : 8) : 0;
-}
-size_t evolve_work_bytes_full(int n, int state_dtype) {
-  const size_t alt = alt_bytes(n, state_dtype);
-  return alt ? alt_offset(n, state_dtype) + alt : evolve_work_bytes(n, state_dtype);
-}
 size_t partials_bytes(int n, int state_dtype) { return evolve_work(n, 1, 0, state_dtype).partials_bytes; }
 
 // Gradient workspace: [forward evolve workspace][p parameter rows][p table rows]
@@ -1011,9 +860,6 @@ int qaoa_workspace_bytes(int op, int n, int state_dtype, int diag_dtype, size_t*
       *bytes = diag_dtype == QAOA_DIAG_F64 ? 0 : diag_dtype == QAOA_DIAG_I32 ? kStatWork : 4 * N + kStatWork;
       return QAOA_OK;
     case QAOA_OP_EVOLVE:
-      if (!valid_state_dtype(state_dtype)) return fail(QAOA_ERR_INVALID, "bad state dtype %d", state_dtype);
-      *bytes = evolve_work_bytes_full(n, state_dtype);
-      return QAOA_OK;
     case QAOA_OP_EXPECTATION:
     case QAOA_OP_GRAD: {
       if (!valid_state_dtype(state_dtype)) return fail(QAOA_ERR_INVALID, "bad state dtype %d", state_dtype);
@@ -1214,7 +1060,7 @@ static int enqueue_expectation(int n, const void* d_state, int sdt, const void* 
 static int enqueue_evolve(int n, int p, int batch, const double* h_gamma, const double* h_beta, const double* d_gamma,
                           const double* d_beta, const void* d_diag, int diag_dtype, double diag_offset,
                           void* d_states, int state_dtype, int init, double* d_out, int G, void* d_work,
-                          Tuning tn, hipStream_t st, void* d_alt = nullptr) {
+                          Tuning tn, hipStream_t st) {
   const uint64_t N = (uint64_t)1 << n;
   const size_t S = state_elem_bytes(state_dtype);
   const bool host_angles = (h_gamma != nullptr);
@@ -1259,16 +1105,11 @@ static int enqueue_evolve(int n, int p, int batch, const double* h_gamma, const 
   const std::vector<SweepStep> sched =
       pl.single ? std::vector<SweepStep>()
                 : sweep_schedule((int)pl.sweeps.size(), p, init != 0, d_out != nullptr, tn.fuse);
-  // a second state buffer (single evaluations only) lets short-run sweeps write whole lines
-  const std::vector<LaunchLayouts> lay = plan_layouts(n, pl, sched, S, d_alt != nullptr && batch == 1);
   int rc = QAOA_OK;
   for (int s0 = 0; s0 < batch; s0 += G) {
     const uint32_t sets = (uint32_t)std::min(G, batch - s0);
     a.set0 = host_angles ? 0 : s0;
-    char* const main_psi = reinterpret_cast<char*>(d_states) + (size_t)s0 * N * S;
-    char* const alt_psi = reinterpret_cast<char*>(d_alt);
-    a.psi = main_psi;
-    a.psi_out = main_psi;
+    a.psi = reinterpret_cast<char*>(d_states) + (size_t)s0 * N * S;
     a.partials = partials + (size_t)s0 * ew.partials_stride;
     uint64_t last_blocks = 1;
     size_t next = 0;  // next schedule step
@@ -1291,10 +1132,6 @@ static int enqueue_evolve(int n, int p, int batch, const double* h_gamma, const 
       for (; next < sched.size() && sched[next].layer < l0 + nl; ++next) {
         const SweepStep& stp = sched[next];
         a.g = pl.sweeps[stp.sweep];
-        a.ld = lay[next].ld;
-        a.st = lay[next].st;
-        a.psi = lay[next].ld_alt ? alt_psi : main_psi;
-        a.psi_out = lay[next].st_alt ? alt_psi : main_psi;
         a.layer0 = host_angles ? stp.layer - l0 : stp.layer;
         a.flags = stp.flags;
         last_blocks = plan_blocks(n, a.g);
@@ -1341,12 +1178,8 @@ int qaoa_evolve(int n, int p, const double* gamma, const double* beta, const voi
     return QAOA_OK;
   }
 
-  const size_t alt = alt_bytes(n, state_dtype);
-  void* d_alt = (alt && work_bytes >= alt_offset(n, state_dtype) + alt)
-                    ? reinterpret_cast<char*>(d_work) + alt_offset(n, state_dtype)
-                    : nullptr;
   return enqueue_evolve(n, p, 1, gamma, beta, nullptr, nullptr, d_diag, diag_dtype, diag_offset, d_state, state_dtype,
-                        init, d_out, 1, d_work, tuning_now(), st, d_alt);
+                        init, d_out, 1, d_work, tuning_now(), st);
 }
 
 }  // extern "C"
@@ -1527,25 +1360,6 @@ int qaoa_schedule_describe(int kind, int n, int p, int state_dtype, int init, in
   for (const auto& s : sched) {
     const int v[3] = {s.sweep, s.layer, s.flags};
     for (int j = 0; j < 3; ++j, ++i)
-      if (out && i < cap) out[i] = v[j];
-  }
-  return i;
-}
-
-int qaoa_layout_describe(int n, int p, int state_dtype, int init, int reduce, int alt, int* out, int cap) {
-  if (n < 1 || n > QAOA_MAX_QUBITS) return -fail(QAOA_ERR_INVALID, "n=%d out of range", n);
-  if (p < 0) return -fail(QAOA_ERR_INVALID, "p < 0");
-  if (!valid_state_dtype(state_dtype)) return -fail(QAOA_ERR_INVALID, "bad state dtype %d", state_dtype);
-  const Tuning tn = tuning_now();
-  const Plan pl = state_plan(n, state_dtype, tn.wide);
-  if (pl.single) return 0;
-  const std::vector<SweepStep> sched =
-      sweep_schedule((int)pl.sweeps.size(), p, init != 0, reduce != 0, tn.fuse);
-  const std::vector<LaunchLayouts> lay = plan_layouts(n, pl, sched, state_elem_bytes(state_dtype), alt != 0);
-  int i = 0;
-  for (const auto& l : lay) {
-    const int v[10] = {l.ld.R, l.ld.hA, l.ld.qA, l.ld.qB, l.ld_alt, l.st.R, l.st.hA, l.st.qA, l.st.qB, l.st_alt};
-    for (int j = 0; j < 10; ++j, ++i)
       if (out && i < cap) out[i] = v[j];
   }
   return i;
@@ -1733,9 +1547,8 @@ int qaoa_grad(int n, int p, const double* gamma, const double* beta, const void*
 
   // forward pass: psi_p in d_state, (E, norm) in d_out[0..1] (d_out[1] is
   // overwritten by the gradient below)
-  // (d_adj is free until the reverse pass: it serves as the second state buffer)
   rc = enqueue_evolve(n, p, 1, gamma, beta, nullptr, nullptr, d_diag, diag_dtype, diag_offset, d_state, state_dtype, 1,
-                      d_out, 1, d_work, tn, st, d_adj);
+                      d_out, 1, d_work, tn, st);
   if (rc) return rc;
 
   // parameter rows and tables of all p layers

@@ -75,48 +75,26 @@ __device__ __forceinline__ uint32_t thr_part(uint32_t tid, int w) {
   return (tid & ((1u << w) - 1u)) | ((tid >> w) << (w + EB));
 }
 
-// Where a tile's bits sit among the bits of an element's position in the
-// state buffer: tile bits [0, R) at bits [0, R), [R, R + hA) at [qA, qA + hA),
-// [R + hA, tb) at [qB, ...).  TileGeom's own R, hA, qA, qB describe the natural
-// layout (position = global index); a launch may read or write the state in
-// another bit order (a rotated layout, planned on the host), described the same
-// way for the same tile.
-struct Layout {
-  int R, hA, qA, qB;
-};
-
-// Position offset of tile element t relative to the block base.  The map sends
-// tile bits to disjoint position bits, so off(a | b) = off(a) + off(b) for
-// disjoint a, b: addresses split into a per-thread part and a per-register
-// part that is uniform across the workgroup.
-__host__ __device__ __forceinline__ uint64_t tile_off_l(uint32_t t, const Layout& l) {
-  const uint32_t rm = (1u << l.R) - 1u, am = (1u << l.hA) - 1u;
-  return (uint64_t)(t & rm) | ((uint64_t)((t >> l.R) & am) << l.qA) | ((uint64_t)(t >> (l.R + l.hA)) << l.qB);
+// Global offset of tile element t relative to the block base.  tile_off maps
+// tile bits to disjoint global bits, so tile_off(a | b) = tile_off(a) +
+// tile_off(b) for disjoint a, b: addresses split into a per-thread part and a
+// per-register part that is uniform across the workgroup.
+__host__ __device__ __forceinline__ uint64_t tile_off(uint32_t t, const TileGeom& g) {
+  const uint32_t rm = (1u << g.R) - 1u, am = (1u << g.hA) - 1u;
+  return (uint64_t)(t & rm) | ((uint64_t)((t >> g.R) & am) << g.qA) | ((uint64_t)(t >> (g.R + g.hA)) << g.qB);
 }
 
-// Position of element 0 of block b: b's bits fill the gaps [R, qA),
-// [qA + hA, qB) and [qB + hB, ...) in that order.
-__host__ __device__ __forceinline__ uint64_t block_base_l(uint64_t b, int tb, const Layout& l) {
-  const int g1 = l.qA - l.R;
-  const int g2 = l.qB - (l.qA + l.hA);
-  const int topB = l.qB + (tb - l.R - l.hA);
+// Global index of element 0 of block b: b's bits fill the gaps [R, qA),
+// [qA + hA, qB) and [qB + hB, n) in that order.
+__device__ __forceinline__ uint64_t block_base(uint64_t b, const TileGeom& g) {
+  const int g1 = g.qA - g.R;
+  const int g2 = g.qB - (g.qA + g.hA);
+  const int topB = g.qB + (g.tb - g.R - g.hA);
   const uint64_t lo = b & ((1ull << g1) - 1ull);
   b >>= g1;
   const uint64_t mid = b & ((1ull << g2) - 1ull);
   b >>= g2;
-  return (lo << l.R) | (mid << (l.qA + l.hA)) | (b << topB);
-}
-
-__host__ __device__ __forceinline__ Layout natural_layout(const TileGeom& g) { return Layout{g.R, g.hA, g.qA, g.qB}; }
-
-// Global offset of tile element t relative to the block base (natural layout).
-__host__ __device__ __forceinline__ uint64_t tile_off(uint32_t t, const TileGeom& g) {
-  return tile_off_l(t, natural_layout(g));
-}
-
-// Global index of element 0 of block b (natural layout).
-__host__ __device__ __forceinline__ uint64_t block_base(uint64_t b, const TileGeom& g) {
-  return block_base_l(b, g.tb, natural_layout(g));
+  return (lo << g.R) | (mid << (g.qA + g.hA)) | (b << topB);
 }
 
 // LDS position of tile element t for tiles held as 2^eb elements per thread:

@@ -44,17 +44,12 @@ def test_workspace_bytes():
     # phase tables (3 x 256 + 4 x 16 entries) of 33 layers (a chunk of 32 and the next one) + the
     # first stage of the two-stage reduction.  The partials cover the most workgroups of either plan
     # (2^12-element tiles: 2^14 workgroups at n=26), so the size does not depend on the tuning knobs.
-    # At n=26 complex128 the evolve workspace also holds a second state buffer
-    # (256-byte aligned after that part), used by the 64-byte-run sweep to write
-    # whole lines.
     want = 16 * (1 << 14) + 1280 + 33 * 832 * 16 + 16 * 1024
-    want_full = (want + 255) // 256 * 256 + 16 * (1 << 26)
     grad_sizes = set()
     for wide in (0, 1):
         for fuse in (0, 1):
             with _lib.tuning(wide_tiles=wide, fuse_layers=fuse):
-                assert _lib.workspace_bytes(_lib.QAOA_OP_EXPECTATION, 26, _lib.QAOA_C128) == want
-                assert _lib.workspace_bytes(_lib.QAOA_OP_EVOLVE, 26, _lib.QAOA_C128) == want_full
+                assert _lib.workspace_bytes(_lib.QAOA_OP_EVOLVE, 26, _lib.QAOA_C128) == want
                 grad_sizes.add(_lib.grad_workspace_bytes(24, 20, _lib.QAOA_C128, _lib.QAOA_DIAG_I32))
     assert len(grad_sizes) == 1
     assert _lib.workspace_bytes(_lib.QAOA_OP_PRECOMPUTE, 20, diag_dtype=_lib.QAOA_DIAG_F64) == 0
