@@ -574,15 +574,14 @@ __device__ __forceinline__ void butterflies(double (&vr)[1 << EB], double (&vi)[
 // Every register bit of a chunk takes a butterfly; bits outside [jlo, jhi)
 // take the identity (t = 0 gives exactly (y0, y1)).  Straight-line code: a
 // branch per bit made the compiler copy all 16 elements after each butterfly.
-// When PHI > PLO the caller guarantees that the last chunk (in plan order) has
-// jlo = PLO, jhi = PHI; that chunk is then applied outside the loop with only
-// its own butterflies (plans end with a chunk of one or two bits).
+// When PHI > PLO the caller guarantees that chunk g.part has jlo = PLO,
+// jhi = PHI; that chunk is then applied outside the loops with only its own
+// butterflies (plans have at most one such chunk of one to three bits).
 template <class S, int EB, bool REV = false, int PLO = 0, int PHI = 0>
 __device__ __forceinline__ int apply_mixer(double (&vr)[1 << EB], double (&vi)[1 << EB], typename S::L* lds,
                                            const TileGeom& g, uint32_t tid, int w, double tn, uint32_t& pcur) {
   constexpr int E = 1 << EB;
   constexpr bool kPart = PHI > PLO;
-  const int nloop = kPart ? g.nchunks - 1 : g.nchunks;
   auto to_window = [&](int wt) {
     if (wt != w) {
       const uint32_t pt = lds_tpart<S, EB>(tid, wt);
@@ -591,12 +590,7 @@ __device__ __forceinline__ int apply_mixer(double (&vr)[1 << EB], double (&vi)[1
       pcur = pt;
     }
   };
-  if constexpr (kPart && REV) {
-    to_window(g.chunk[g.nchunks - 1].w);
-    butterflies<EB, PLO, PHI>(vr, vi, tn);
-  }
-  for (int i = 0; i < nloop; ++i) {
-    const Chunk ch = g.chunk[REV ? nloop - 1 - i : i];
+  auto chunk = [&](const Chunk ch) {
     to_window(ch.w);
 #pragma unroll
     for (int j = 0; j < EB; ++j) {
@@ -606,10 +600,25 @@ __device__ __forceinline__ int apply_mixer(double (&vr)[1 << EB], double (&vi)[1
         if (!(k & (1 << j))) rx_pair_t(vr[k], vi[k], vr[k | (1 << j)], vi[k | (1 << j)], tj);
       }
     }
-  }
-  if constexpr (kPart && !REV) {
-    to_window(g.chunk[g.nchunks - 1].w);
-    butterflies<EB, PLO, PHI>(vr, vi, tn);
+  };
+  const int nc = g.nchunks;
+  if constexpr (!kPart) {
+    for (int i = 0; i < nc; ++i) chunk(g.chunk[REV ? nc - 1 - i : i]);
+  } else {
+    // the short chunk g.part (bits [PLO, PHI) of its window) between two loops
+    // of ordinary chunks, so neither loop branches on the chunk kind
+    const int pi = g.part;
+    if constexpr (!REV) {
+      for (int i = 0; i < pi; ++i) chunk(g.chunk[i]);
+      to_window(g.chunk[pi].w);
+      butterflies<EB, PLO, PHI>(vr, vi, tn);
+      for (int i = pi + 1; i < nc; ++i) chunk(g.chunk[i]);
+    } else {
+      for (int i = nc - 1; i > pi; --i) chunk(g.chunk[i]);
+      to_window(g.chunk[pi].w);
+      butterflies<EB, PLO, PHI>(vr, vi, tn);
+      for (int i = pi - 1; i >= 0; --i) chunk(g.chunk[i]);
+    }
   }
   return w;
 }
@@ -664,7 +673,7 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
   const LayerParams lq_early = kEarlyNext ? layer_params(a, set, 1) : lp;
 
   double vr[E], vi[E];
-  const int w_load = a.g.tb - EB;
+  const int w_load = a.g.chunk[0].w;  // the load mapping: the first chunk's window
   int w = w_load;
   // EXPV: the cost values are read with the state, in the coalesced load
   // mapping, and the tile returns to that mapping for the reduction.  FUSE:

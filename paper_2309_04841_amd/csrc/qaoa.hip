@@ -76,22 +76,59 @@ int min_passenger_bits(size_t elem_bytes, size_t run_bytes = 128) {
 // windows w <= qk::kLocalWin where they can: in all such windows the thread
 // bits >= 6 (a thread's wave) map to the same tile bits, so changing between
 // them moves data only within each wave and needs no workgroup barrier.
-qk::TileGeom make_geom(int tb, int R, int hA, int qA, int qB, int act_lo, int eb, int store_min_bits) {
+//
+// local_load (tiles of 1024 threads, whose top window is not wave-local): the
+// lower active bits are split around window kLocalWin instead, whose chunk
+// comes first and is the load (and fused store) window, then the other lower
+// chunks (a short one last among them), then the top chunk.  Each wave then
+// loads, applies the local chunks and, at the end, stores without waiting for
+// the others; only the changes into and out of the top window meet at
+// barriers.  In window kLocalWin the lanes are tile bits [0, 6), so loads stay
+// coalesced as in the top window.
+qk::TileGeom make_geom(int tb, int R, int hA, int qA, int qB, int act_lo, int eb, int store_min_bits,
+                       bool local_load = false) {
   qk::TileGeom g{};
-  g.tb = tb; g.R = R; g.hA = hA; g.qA = qA; g.qB = qB; g.act_lo = act_lo; g.nchunks = 0;
+  g.tb = tb; g.R = R; g.hA = hA; g.qA = qA; g.qB = qB; g.act_lo = act_lo; g.nchunks = 0; g.part = -1;
   const int top_w = tb - eb;
   const int lo0 = std::max(act_lo, top_w);
-  g.chunk[g.nchunks++] = qk::Chunk{(int8_t)top_w, (int8_t)(lo0 - top_w), (int8_t)eb, 0};
-  int rlo = act_lo;
-  const int rhi = lo0;
-  while (rlo < rhi) {
-    const int chi = std::min(rlo + eb, rhi);
-    // w <= rlo < top_w, covers [rlo, chi).  A short last chunk sits at the top
-    // of its window (jhi = eb), the form the fused kernels specialise.
-    const int w = (chi - rlo < eb && chi >= eb) ? chi - eb : std::max(chi - eb, std::min(rlo, qk::kLocalWin));
-    g.chunk[g.nchunks++] = qk::Chunk{(int8_t)w, (int8_t)(rlo - w), (int8_t)(chi - w), 0};
-    rlo = chi;
+  const qk::Chunk top{(int8_t)top_w, (int8_t)(lo0 - top_w), (int8_t)eb, 0};
+  // chunks over [lo, hi), bottom-up; a short last one sits at the top of its window
+  // (jhi = eb), the form the fused kernels specialise
+  auto split = [&](int lo, int hi, std::vector<qk::Chunk>& out) {
+    while (lo < hi) {
+      const int chi = std::min(lo + eb, hi);
+      const int w = (chi - lo < eb && chi >= eb) ? chi - eb : std::max(chi - eb, std::min(lo, qk::kLocalWin));
+      out.push_back(qk::Chunk{(int8_t)w, (int8_t)(lo - w), (int8_t)(chi - w), 0});
+      lo = chi;
+    }
+  };
+  auto is_short = [&](const qk::Chunk& c) { return c.jlo > 0 && c.jhi == eb; };
+  const int wl = qk::kLocalWin;
+  if (local_load && top_w > wl + eb - 1 && top.jlo == 0 && act_lo <= wl && lo0 == wl + eb) {
+    std::vector<qk::Chunk> low;
+    split(act_lo, wl, low);
+    int nshort = 0;
+    bool ok = true;
+    for (size_t i = 0; i < low.size(); ++i) {
+      if (is_short(low[i])) { ++nshort; ok = ok && i + 1 == low.size(); }
+      else ok = ok && low[i].jlo == 0 && low[i].jhi == eb;
+    }
+    if (ok && nshort <= 1) {
+      g.chunk[g.nchunks++] = qk::Chunk{(int8_t)wl, 0, (int8_t)eb, 0};
+      for (const auto& c : low) {
+        if (is_short(c)) g.part = g.nchunks;
+        g.chunk[g.nchunks++] = c;
+      }
+      g.chunk[g.nchunks++] = top;
+      g.w_store = top_w;  // coalesced like window kLocalWin; plain sweeps end there
+      return g;
+    }
   }
+  g.chunk[g.nchunks++] = top;
+  std::vector<qk::Chunk> low;
+  split(act_lo, lo0, low);
+  for (const auto& c : low) g.chunk[g.nchunks++] = c;
+  if (is_short(g.chunk[g.nchunks - 1])) g.part = g.nchunks - 1;
   const int last_w = g.chunk[g.nchunks - 1].w;
   g.w_store = (std::min(last_w, R) >= store_min_bits || last_w == top_w) ? last_w : top_w;
   return g;
@@ -118,7 +155,8 @@ int page_bit(size_t elem_bytes) {
 // qubits.  m0 and the split are chosen to minimise the largest number of
 // page-selecting qubits in any sweep (2^that = pages a workgroup touches),
 // keeping the sweep count of the plain split.
-Plan make_plan(int n, size_t elem_bytes, int eb = kEB, int tb_cap = 0, size_t run_bytes = 128) {
+Plan make_plan(int n, size_t elem_bytes, int eb = kEB, int tb_cap = 0, size_t run_bytes = 128,
+               bool local_load = false) {
   Plan pl;
   pl.wide = false;
   const int tbmax = tb_cap ? tb_cap : tile_bits_for_bytes(elem_bytes, 9 + eb);
@@ -160,13 +198,13 @@ Plan make_plan(int n, size_t elem_bytes, int eb = kEB, int tb_cap = 0, size_t ru
   }
   const int m0 = best_m0, R0 = tbmax - m0;
   // first sweep: run [0, R0) + segment [n - m0, n), all active
-  pl.sweeps.push_back(make_geom(tbmax, R0, m0, n - m0, n, 0, eb, smin));
+  pl.sweeps.push_back(make_geom(tbmax, R0, m0, n - m0, n, 0, eb, smin, local_load));
   int xa = R0, xb = std::max(pb, R0);
   for (int i = 0; i < k - 1; ++i) {
     const int h = best_h[i], bpage = best_b[i], a = h - bpage, P = tbmax - h;
     const int qA = a ? xa : xb;         // an empty segment A sits where B starts
     const int qB = bpage ? xb : qA + a;  // an empty segment B sits where A ends
-    pl.sweeps.push_back(make_geom(tbmax, P, a, qA, qB, P, eb, smin));
+    pl.sweeps.push_back(make_geom(tbmax, P, a, qA, qB, P, eb, smin, local_load));
     xa += a;
     xb += bpage;
   }
@@ -195,7 +233,7 @@ Plan state_plan(int n, int state_dtype, bool wide) {
   Plan best = make_plan(n, S);
   if (state_dtype != QAOA_C128 || n <= kWideTileBits || !wide) return best;
   for (size_t run : {(size_t)128, (size_t)64}) {
-    Plan w = make_plan(n, S, kEB, kWideTileBits, run);
+    Plan w = make_plan(n, S, kEB, kWideTileBits, run, true);
     if (w.sweeps.size() < best.sweeps.size()) {
       w.wide = true;
       best = w;
@@ -469,12 +507,12 @@ void launch_sweep_f(const qk::SweepArgs& a, uint64_t blocks, uint32_t sets, hipS
                      dim3((uint32_t)blocks, sets), dim3(threads), lds, st, with_offsets<S>(a, kEB));
 }
 
-// Sweeps specialise a short last chunk (register bits [1, 4), [2, 4) or
-// [3, 4) of its window: plans put short last chunks at the top of their
-// window), so its other bits take no identity butterflies.
+// Sweeps specialise a plan's short chunk g.part (register bits [1, 4), [2, 4)
+// or [3, 4) of its window: plans put short chunks at the top of their window),
+// so its other bits take no identity butterflies.
 template <class S, class D, bool INIT, bool PHASE, bool EXPV, bool FUSE>
 void launch_sweep_p(const qk::SweepArgs& a, uint64_t blocks, uint32_t sets, hipStream_t st) {
-  const qk::Chunk last = a.g.chunk[a.g.nchunks - 1];
+  const qk::Chunk last = a.g.part >= 0 ? a.g.chunk[a.g.part] : qk::Chunk{0, 0, 0, 0};
   if (last.jhi == kEB && last.jlo == 1) launch_sweep_f<S, D, INIT, PHASE, EXPV, FUSE, 1, 4>(a, blocks, sets, st);
   else if (last.jhi == kEB && last.jlo == 2) launch_sweep_f<S, D, INIT, PHASE, EXPV, FUSE, 2, 4>(a, blocks, sets, st);
   else if (last.jhi == kEB && last.jlo == 3) launch_sweep_f<S, D, INIT, PHASE, EXPV, FUSE, 3, 4>(a, blocks, sets, st);

@@ -53,6 +53,7 @@ struct TileGeom {
   int act_lo;   // active tile bits [act_lo, tb)
   int nchunks;  // chunks per layer
   int w_store;  // window the tile is stored from
+  int part;     // index of the short chunk the fused sweeps specialise (bits [jlo, EB) of its window), or -1
   Chunk chunk[kMaxChunks];
   // Per-register parts of the addresses for register window w, filled on the
   // host (uniform across the workgroup, so the kernels read them with scalar

@@ -292,7 +292,9 @@ def _check_plan(n, plan, elem_bytes, emulate):
         gbits = [global_bit(s, t) for t in range(tb)]
         assert len(set(gbits)) == tb and max(gbits) < n
         assert 0 <= s["w_store"] <= tb - eb
-        assert s["chunks"][0][0] == tb - eb, "first window must be the load mapping"
+        # the first chunk's window is the load mapping: the top window, or (wide
+        # tiles) window 6, whose lanes are tile bits [0, 6) as in the top window
+        assert s["chunks"][0][0] == tb - eb or (wide and s["chunks"][0][0] == 6), "first window must load coalesced"
         for (w, jlo, jhi) in s["chunks"]:
             assert 0 <= w <= tb - eb and 0 <= jlo < jhi <= eb
             for j in range(jlo, jhi):
@@ -584,10 +586,18 @@ def test_tuning_knobs():
 
 
 def test_lower_windows_are_wave_local():
-    # every chunk below the load window uses a window <= 6 in the headline plans
+    # in the headline plans only the top window (tb - 4) is not wave-local: the
+    # other chunks use windows <= 6, and the top chunk comes either first (the
+    # load window) or, when a plan loads in window 6, last
     for n, sdt in ((26, _lib.QAOA_C128), (31, _lib.QAOA_C64), (20, _lib.QAOA_C128)):
         for sw in _lib.plan_describe(n, sdt)["sweeps"]:
-            assert all(w <= 6 for (w, _, _) in sw["chunks"][1:]), (n, sw["chunks"])
+            top = sw["tb"] - 4
+            ws = [w for (w, _, _) in sw["chunks"]]
+            assert all(w <= 6 for w in ws if w != top), (n, sw["chunks"])
+            assert ws.count(top) == 1 and (ws[0] == top or ws[-1] == top), (n, sw["chunks"])
+    a, b = _lib.plan_describe(26, _lib.QAOA_C128)["sweeps"]
+    assert [w for (w, _, _) in a["chunks"]] == [6, 0, 2, 10] and a["chunks"][2] == (2, 2, 4)
+    assert [w for (w, _, _) in b["chunks"]] == [6, 2, 10] and b["w_store"] == 10
 
 
 def test_tile_kernels_have_no_static_lds(tmp_path):
