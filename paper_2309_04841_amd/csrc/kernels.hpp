@@ -34,7 +34,7 @@ enum : int { F_INIT = 1, F_PHASE = 2, F_EXPV = 4, F_FUSE = 8 };
 // ----------------------------------------------------------------------------
 // The state is streamed once per sweep: its loads and stores carry the
 // non-temporal hint so they do not displace the cost vector and tables, which
-// are re-read every layer.
+// are re-read every layer (except in 2^14-element complex128 tiles, below).
 // LDS accesses by byte address.  The tile kernels declare no static LDS, so
 // their dynamic LDS (smem_raw) starts at address 0 and a tile position's byte
 // offset is its LDS address; addressing it directly saves the per-access add of
@@ -109,6 +109,19 @@ struct C64 {  // complex64 storage, FP64 arithmetic in registers
 // imaginary parts, through one 128 KiB buffer of doubles.  Used when the larger
 // tile saves a sweep per layer.
 struct C128W : C128 {
+  // Ordinary (temporal) loads and stores: the sweep with 64-byte runs reads and
+  // writes each 128-byte line in halves from two workgroups, and a line kept in
+  // L2 from its load takes both halves of the store before it is written back
+  // (measured, n=26 complex128: 160.8 -> 167.0 evaluations/s; temporal loads
+  // or stores alone gained nothing)
+  __device__ static __forceinline__ void load(const void* p, uint64_t x, double& r, double& i) {
+    const dvec2 v = *(reinterpret_cast<const dvec2*>(p) + x);
+    r = v.x; i = v.y;
+  }
+  __device__ static __forceinline__ void store(void* p, uint64_t x, double r, double i) {
+    const dvec2 v = {r, i};
+    *(reinterpret_cast<dvec2*>(p) + x) = v;
+  }
   static constexpr int kLdsBytes = 8;
   static constexpr bool kSplit = true;
   static constexpr int kMaxThreads = 1024;
@@ -707,15 +720,16 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
     for (int k = 0; k < E; k += 2)
       cpk[k / 2] = (uint32_t)c16[xb + a.g.goff[wp][k]] | ((uint32_t)c16[xb + a.g.goff[wp][k + 1]] << 16);
   }
-  if constexpr (FUSE && D::kTable) {
-    // the next layer's tables go to LDS now, overlapping the state loads
-    const LayerParams lq0 = kEarlyNext ? lq_early : layer_params(a, set, 1);
+  if constexpr ((FUSE || PHASE) && D::kTable) {
+    // the tables of the phase this launch applies go to LDS now, overlapping
+    // the state loads (FUSE: the next layer's; PHASE: this layer's)
+    const LayerParams lq0 = FUSE ? (kEarlyNext ? lq_early : layer_params(a, set, 1)) : lp;
     for (uint32_t e = tid; e < (uint32_t)kTabEntries; e += blockDim.x) tab[e] = lq0.tab[e];
   }
   if constexpr (PHASE) {
     typename D::RawT pc[E];
     load_cost<D, EB>(pc, a, base, tid, w);
-    phase_from_raw<S, D, EB>(vr, vi, pc, a, lp, tid, tab);
+    phase_from_raw<S, D, EB, D::kTable>(vr, vi, pc, a, lp, tid, tab);
   }
   const int nq = a.g.tb - a.g.act_lo;  // gates per layer in this tile
   uint32_t pcur = lds_tpart<S, EB>(tid, w);
@@ -735,7 +749,10 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
   }
 
   double e_part = 0.0, n_part = 0.0;
-  const int w_out = EXPV ? w_load : (FUSE ? w : a.g.w_store);
+  // wide tiles store from the window their chunk order ends in (the top
+  // window, coalesced, in their plans): no final change of window, whose code
+  // alone made the register allocator spill in these 16-wave kernels
+  const int w_out = EXPV ? w_load : ((FUSE || S::kSplit) ? w : a.g.w_store);
   if (w != w_out) {
     exchange_p<S, EB>(vr, vi, lds, a.g, w, w_out, pcur, lds_tpart<S, EB>(tid, w_out));
     w = w_out;
