@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "tile.hpp"
 
 namespace qk {
@@ -862,33 +864,69 @@ __device__ __forceinline__ double xterm(double pr0, double pi0, double pr1, doub
 // Undo the layer's mixer gates on the tile's active qubits for psi and lambda
 // (gate with -beta), accumulating Im<lambda|X_q|psi> per undone qubit (X_q
 // commutes with every mixer gate, so any point of the undo gives the same value).
-template <class S, int EB, bool REV = false>
+// Each undo gate cos(b) I + i sin(b) X is applied divided by cos(b), as
+// (y0, y1) -> (y0 + i t y1, y1 + i t y0) with t = tan(b): four FMAs per pair
+// and state instead of eight operations.  Within a chunk both states then
+// carry 1/cos(b) per gate already undone, so the X term of a later qubit is
+// scaled back by cos(b)^2 per such gate, and the tile is rescaled by
+// cos(b)^(gates) at the end of each chunk (so the growth stays below
+// |cos b|^-(2 EB) even for b near pi/2).  Bits outside [jlo, jhi) take the
+// identity (t = 0) and add nothing to the X term.
+template <class S, int EB, bool REV = false, int PLO = 0, int PHI = 0>
 __device__ __forceinline__ int undo_mixer(double (&vr)[1 << EB], double (&vi)[1 << EB], double (&lr)[1 << EB],
                                           double (&li)[1 << EB], typename S::L* lds, const TileGeom& g,
-                                          uint32_t tid, int w, double ca, double sb, double& xacc) {
+                                          uint32_t tid, int w, double ca, double tn, double& xacc) {
   constexpr int E = 1 << EB;
-  for (int i = 0; i < g.nchunks; ++i) {
-    const Chunk ch = g.chunk[REV ? g.nchunks - 1 - i : i];
+  constexpr bool kPart = PHI > PLO;
+  const double c2 = ca * ca;
+  // one chunk: register bits [lo, hi) of its window (compile-time bounds for
+  // the specialised short chunk, so its other bits take no identity butterflies)
+  auto chunk = [&](const Chunk ch, auto lo_c, auto hi_c) {
+    constexpr int LO = decltype(lo_c)::value, HI = decltype(hi_c)::value;
     if (ch.w != w) {
       exchange_c<S, EB>(vr, vi, lds, g, tid, w, ch.w);
       exchange_c<S, EB>(lr, li, lds, g, tid, w, ch.w);
       w = ch.w;
     }
-    // straight-line: bits outside [jlo, jhi) take the identity gate (1, 0)
-    // and add nothing to the X term
+    double s2 = 1.0;  // cos(b)^2 per gate undone so far in this chunk
+    double cs = 1.0;  // cos(b) per gate undone so far in this chunk
 #pragma unroll
     for (int j = 0; j < EB; ++j) {
-      const bool on = (j >= ch.jlo && j < ch.jhi);
-      const double aj = on ? ca : 1.0, sj = on ? -sb : 0.0, mj = on ? 1.0 : 0.0;
+      if (HI > LO && (j < LO || j >= HI)) continue;
+      const bool on = HI > LO || (j >= ch.jlo && j < ch.jhi);
+      const double tj = on ? -tn : 0.0, mj = on ? s2 : 0.0;
 #pragma unroll
       for (int k = 0; k < E; ++k) {
         if (!(k & (1 << j))) {
           const int k1 = k | (1 << j);
           xacc = fma(mj, xterm(vr[k], vi[k], vr[k1], vi[k1], lr[k], li[k], lr[k1], li[k1]), xacc);
-          rx_pair(vr[k], vi[k], vr[k1], vi[k1], aj, sj);
-          rx_pair(lr[k], li[k], lr[k1], li[k1], aj, sj);
+          rx_pair_t(vr[k], vi[k], vr[k1], vi[k1], tj);
+          rx_pair_t(lr[k], li[k], lr[k1], li[k1], tj);
         }
       }
+      s2 = on ? s2 * c2 : s2;
+      cs = on ? cs * ca : cs;
+    }
+    scale_tile(vr, vi, cs);
+    scale_tile(lr, li, cs);
+  };
+  using Z = std::integral_constant<int, 0>;
+  using PL = std::integral_constant<int, PLO>;
+  using PH = std::integral_constant<int, PHI>;
+  const int nc = g.nchunks;
+  if constexpr (!kPart) {
+    for (int i = 0; i < nc; ++i) chunk(g.chunk[REV ? nc - 1 - i : i], Z{}, Z{});
+  } else {
+    // the short chunk g.part between two loops of ordinary chunks
+    const int pi = g.part;
+    if constexpr (!REV) {
+      for (int i = 0; i < pi; ++i) chunk(g.chunk[i], Z{}, Z{});
+      chunk(g.chunk[pi], PL{}, PH{});
+      for (int i = pi + 1; i < nc; ++i) chunk(g.chunk[i], Z{}, Z{});
+    } else {
+      for (int i = nc - 1; i > pi; --i) chunk(g.chunk[i], Z{}, Z{});
+      chunk(g.chunk[pi], PL{}, PH{});
+      for (int i = pi - 1; i >= 0; --i) chunk(g.chunk[i], Z{}, Z{});
     }
   }
   return w;
@@ -945,7 +983,7 @@ __device__ __forceinline__ void undo_phase(double (&vr)[1 << EB], double (&vi)[1
 // time).  complex128 keeps its registers: capped, its fused variant spilled
 // 168 bytes per lane, the spill traffic raised the measured HBM bytes per
 // launch by a third, and the gradient gained only 2.6 %.
-template <class S, class D, int EB, bool FIRST, bool PHASE, bool FUSE>
+template <class S, class D, int EB, bool FIRST, bool PHASE, bool FUSE, int PLO = 0, int PHI = 0>
 __global__ void __launch_bounds__(512, S::kAdjMinWavesPerSimd) qaoa_adjoint_kernel(const AdjArgs a) {
   constexpr int E = 1 << EB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -981,12 +1019,12 @@ __global__ void __launch_bounds__(512, S::kAdjMinWavesPerSimd) qaoa_adjoint_kern
     if constexpr (FUSE) load_cost_g<D, EB>(cv, a.diag, base, tid, a.g.chunk[a.g.nchunks - 1].w, a.g);
   }
   double xacc = 0.0, gacc = 0.0, xacc2 = 0.0;
-  w = undo_mixer<S, EB>(vr, vi, lr, li, lds, a.g, tid, w, lp.ca, lp.sb, xacc);
+  w = undo_mixer<S, EB, false, PLO, PHI>(vr, vi, lr, li, lds, a.g, tid, w, lp.ca, lp.tn, xacc);
   if constexpr (FUSE) {
     undo_phase<D, EB>(vr, vi, lr, li, cv, a, lp, tab, tid, gacc);
     const size_t r1 = r - 1;
-    w = undo_mixer<S, EB, true>(vr, vi, lr, li, lds, a.g, tid, w, a.pset[kParamRow * r1 + 1],
-                                      a.pset[kParamRow * r1 + 2], xacc2);
+    w = undo_mixer<S, EB, true, PLO, PHI>(vr, vi, lr, li, lds, a.g, tid, w, a.pset[kParamRow * r1 + 1],
+                                          a.pset[kParamRow * r1 + 3], xacc2);
   }
   const int w_out = PHASE ? w_load : (FUSE ? w : a.g.w_store);
   if (w != w_out) {
@@ -1162,7 +1200,7 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_tile_kernel(const AdjArgs a)
     const double* prow = a.pset + kParamRow * (size_t)l;
     const LayerParams lp{prow[0], prow[1], prow[2], prow[3], a.ptab + (size_t)l * kTabRow};
     double xacc = 0.0, gacc = 0.0;
-    w = undo_mixer<S, EB>(vr, vi, lr, li, lds, a.g, tid, w, lp.ca, lp.sb, xacc);
+    w = undo_mixer<S, EB>(vr, vi, lr, li, lds, a.g, tid, w, lp.ca, lp.tn, xacc);
     if (w != w_load) {
       exchange_c<S, EB>(vr, vi, lds, a.g, tid, w, w_load);
       exchange_c<S, EB>(lr, li, lds, a.g, tid, w, w_load);

@@ -304,7 +304,19 @@ std::vector<SweepStep> sweep_schedule(int nsw, int p, bool init, bool expv, bool
 
 // Reverse (adjoint) sweeps hold two states per thread: 8 elements of each.
 constexpr int kEBAdj = 3;
-Plan adjoint_plan(int n, size_t state_bytes) { return make_plan(n, state_bytes, kEBAdj); }
+// complex128 reverse sweeps use 2^11-element tiles when that costs no sweep:
+// their fused variant needs ~235 registers per lane, so a 2^12-element tile's
+// 512 threads fill a compute unit alone, while two 256-thread workgroups of
+// 2^11 elements share it and overlap one's memory phase with the other's
+// arithmetic (LABS n=24 p=20 gradient: 13.2 -> 12.4 ms).
+Plan adjoint_plan(int n, size_t state_bytes) {
+  Plan a = make_plan(n, state_bytes, kEBAdj);
+  if (state_bytes == 16 && !a.single) {
+    Plan b = make_plan(n, state_bytes, kEBAdj, 11);
+    if (!b.single && b.sweeps.size() <= a.sweeps.size()) return b;
+  }
+  return a;
+}
 
 // ---------------------------------------------------------------------------
 // XY mixer plans (Section 3.2).  One layer is an ordered edge sequence
@@ -626,14 +638,23 @@ void launch_xy(const qk::XyArgs& a, int sdt, int ddt, int eb, uint64_t blocks, u
   }
 }
 
-template <class S, class D, bool FIRST, bool PHASE, bool FUSE>
-void launch_adj_f(const qk::AdjArgs& a, uint64_t blocks, hipStream_t st) {
+template <class S, class D, bool FIRST, bool PHASE, bool FUSE, int PLO = 0, int PHI = 0>
+void launch_adj_ff(const qk::AdjArgs& a, uint64_t blocks, hipStream_t st) {
   const uint32_t threads = 1u << (a.g.tb - kEBAdj);
   const size_t tile = ((size_t)1 << a.g.tb) * S::kLdsBytes;
   const size_t lds = std::max<size_t>(tile + D::kTabLds * sizeof(double2) + 16 * sizeof(uint32_t),
                                       std::max<size_t>(16, 2 * threads) * sizeof(double));
-  hipLaunchKernelGGL((qk::qaoa_adjoint_kernel<S, D, kEBAdj, FIRST, PHASE, FUSE>), dim3((uint32_t)blocks),
+  hipLaunchKernelGGL((qk::qaoa_adjoint_kernel<S, D, kEBAdj, FIRST, PHASE, FUSE, PLO, PHI>), dim3((uint32_t)blocks),
                      dim3(threads), lds, st, with_offsets<S>(a, kEBAdj));
+}
+
+// Reverse sweeps specialise a plan's short chunk (register bits [1, 3) or [2, 3)).
+template <class S, class D, bool FIRST, bool PHASE, bool FUSE>
+void launch_adj_f(const qk::AdjArgs& a, uint64_t blocks, hipStream_t st) {
+  const qk::Chunk c = a.g.part >= 0 ? a.g.chunk[a.g.part] : qk::Chunk{0, 0, 0, 0};
+  if (c.jhi == kEBAdj && c.jlo == 1) launch_adj_ff<S, D, FIRST, PHASE, FUSE, 1, kEBAdj>(a, blocks, st);
+  else if (c.jhi == kEBAdj && c.jlo == 2) launch_adj_ff<S, D, FIRST, PHASE, FUSE, 2, kEBAdj>(a, blocks, st);
+  else launch_adj_ff<S, D, FIRST, PHASE, FUSE>(a, blocks, st);
 }
 
 template <class S, class D>
