@@ -254,7 +254,7 @@ def bench_batch(args):
     return {"metric": "batched QAOA evals/s, weighted MaxCut G(22,0.3) p=6, 512 sets", "value": batch / t_batch,
             "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": ms_batch, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "f64", "data": "synthetic",
+            "dtype": "f32", "data": "synthetic",
             "config": {"workload": cfg["name"], "n": n, "p": p, "sets": batch, "state": "complex64",
                        "cost_vector": "int32", "sets_per_pass": spp, "fuse_layers": best["fuse_layers"],
                        "wide_tiles": best["wide_tiles"], "timing": "HIP graph replay"},
@@ -462,8 +462,9 @@ def bench_serve(args):
     main_mix = mixes["mix"]
     return {"metric": "served QAOA requests/s (60% objective / 40% gradient, n 16..30, p 1..20)",
             "value": main_mix["capacity_requests_per_s"], "unit": "requests/s", "n_gpus": 1,
-            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": "serve_mix", "state": "complex64", "streams": 4, "max_in_flight": 16},
+            "higher_is_better": True, "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": "serve_mix", "state": "complex64", "streams": 4, "max_in_flight": 16,
+                       "arithmetic": "forward sweeps FP32, gradient sweeps FP64"},
             "p50_ms": main_mix["p50_ms"], "p99_ms": main_mix["p99_ms"], "mixes": mixes}
 
 
@@ -707,7 +708,9 @@ def measure_eval(config, diag_name, steps, warmup, cpu_budget):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        # complex64 transverse-field sweeps compute in FP32 (FP64 for layers
+        # with |tan beta| > 64, none in these ramps); the rest in FP64
+        "dtype": "f32" if (cfg["dtype"] == "complex64" and not mixer) else "f64",
         "data": "synthetic",
         "config": {
             "workload": cfg["name"] + (f"+{mixer}" if mixer else ""), "problem": "LABS", "n": n, "p": p,

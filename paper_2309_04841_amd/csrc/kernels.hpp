@@ -51,6 +51,9 @@ __device__ __forceinline__ lds_f64* lds_d(uint32_t addr) { return (lds_f64*)(uin
 
 struct C128 {  // complex128: (double re, double im)
   using L = double2;
+  using R = double;    // arithmetic type of the forward sweeps
+  using Tab = double2; // their LDS phase-table entries
+  static constexpr bool kDualPrecision = false;
   static constexpr int kBytes = 16;
   static constexpr int kLdsBytes = 16;   // LDS bytes per tile element
   static constexpr bool kSplit = false;  // exchanges move whole elements
@@ -79,8 +82,16 @@ struct C128 {  // complex128: (double re, double im)
   }
 };
 
-struct C64 {  // complex64 storage, FP64 arithmetic in registers
+// complex64 storage.  The forward sweeps compute in FP32 (R, Tab), which leaves
+// out the conversions at every load, store and window change (LABS n=31
+// p=10: 5.86 -> 6.54 evaluations/s), except for layers with |tan beta| above
+// kTanMaxF32; the reverse (gradient) sweeps and the XY kernels keep FP64
+// registers (the double overloads below).
+struct C64 {
   using L = float2;
+  using R = float;
+  using Tab = float2;
+  static constexpr bool kDualPrecision = true;  // FP64 sweeps for large |tan beta|
   static constexpr int kBytes = 8;
   static constexpr int kLdsBytes = 8;
   static constexpr bool kSplit = false;
@@ -103,6 +114,22 @@ struct C64 {  // complex64 storage, FP64 arithmetic in registers
   __device__ static __forceinline__ void lget(const L*, uint32_t off, double& r, double& i) {
     const fvec2 v = *(lds_f32x2*)(uintptr_t)off;
     r = (double)v.x; i = (double)v.y;
+  }
+  __device__ static __forceinline__ void load(const void* p, uint64_t x, float& r, float& i) {
+    const fvec2 v = __builtin_nontemporal_load(reinterpret_cast<const fvec2*>(p) + x);
+    r = v.x; i = v.y;
+  }
+  __device__ static __forceinline__ void store(void* p, uint64_t x, float r, float i) {
+    const fvec2 v = {r, i};
+    __builtin_nontemporal_store(v, reinterpret_cast<fvec2*>(p) + x);
+  }
+  __device__ static __forceinline__ void lput(L*, uint32_t off, float r, float i) {
+    const fvec2 v = {r, i};
+    *(lds_f32x2*)(uintptr_t)off = v;
+  }
+  __device__ static __forceinline__ void lget(const L*, uint32_t off, float& r, float& i) {
+    const fvec2 v = *(lds_f32x2*)(uintptr_t)off;
+    r = v.x; i = v.y;
   }
 };
 
@@ -271,18 +298,28 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Threads per workgroup, read from the dispatch packet (workgroup_size_x, bytes
+// 4-5) with a scalar load.  blockDim.x inside an inlined helper becomes a
+// per-lane load that allows for a partial last workgroup, and its wait for
+// vector memory (vmcnt(0)) would stall on the tile's state loads in flight;
+// every launch here has whole workgroups.
+__device__ __forceinline__ uint32_t wg_size() {
+  typedef __attribute__((address_space(4))) const uint16_t packet_u16;
+  return ((packet_u16*)__builtin_amdgcn_dispatch_ptr())[2];
+}
+
 // Sums (x, y) over the workgroup in a fixed order; result valid in thread 0.
 // `scratch` holds 2 doubles per wave (2 per thread when the workgroup is a
 // single partial wave).  Ends with all threads past a barrier.
 __device__ __forceinline__ void block_sum2(double& x, double& y, double* scratch) {
-  if (blockDim.x < 64) {
+  if (wg_size() < 64) {
     // partial wave: no cross-lane shuffles over inactive lanes
     scratch[2 * threadIdx.x] = x;
     scratch[2 * threadIdx.x + 1] = y;
     __syncthreads();
     if (threadIdx.x == 0) {
       double sx = 0.0, sy = 0.0;
-      for (uint32_t i = 0; i < blockDim.x; ++i) { sx += scratch[2 * i]; sy += scratch[2 * i + 1]; }
+      for (uint32_t i = 0; i < wg_size(); ++i) { sx += scratch[2 * i]; sy += scratch[2 * i + 1]; }
       x = sx; y = sy;
     }
     __syncthreads();
@@ -294,7 +331,7 @@ __device__ __forceinline__ void block_sum2(double& x, double& y, double* scratch
   if (lane == 0) { scratch[2 * wv] = x; scratch[2 * wv + 1] = y; }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t nw = (blockDim.x + 63u) >> 6;
+    const uint32_t nw = (wg_size() + 63u) >> 6;
     double sx = 0.0, sy = 0.0;
     for (uint32_t i = 0; i < nw; ++i) { sx += scratch[2 * i]; sy += scratch[2 * i + 1]; }
     x = sx; y = sy;
@@ -327,6 +364,9 @@ struct SweepArgs {
   uint64_t partials_stride;
 };
 
+// Largest |tan beta| for which complex64 sweeps compute in FP32.
+constexpr double kTanMaxF32 = 64.0;
+
 struct LayerParams {
   double g, ca, sb, tn;  // gamma, cos beta, sin beta, tan beta
   const double2* tab;
@@ -354,11 +394,12 @@ __device__ __forceinline__ void rx_pair(double& r0, double& i0, double& r1, doub
 // Every element carries the same factor, so relative precision is unchanged;
 // in double the growth 1/|cos b|^k stays finite for every representable b and
 // k <= 14 (|cos b| >= ~1e-19), and tiles are rescaled before the next layer.
-__device__ __forceinline__ void rx_pair_t(double& r0, double& i0, double& r1, double& i1, double t) {
-  const double nr0 = fma(t, i1, r0);
-  const double ni0 = fma(-t, r1, i0);
-  const double nr1 = fma(t, i0, r1);
-  const double ni1 = fma(-t, r0, i1);
+template <class T>
+__device__ __forceinline__ void rx_pair_t(T& r0, T& i0, T& r1, T& i1, T t) {
+  const T nr0 = fma(t, i1, r0);
+  const T ni0 = fma(-t, r1, i0);
+  const T nr1 = fma(t, i0, r1);
+  const T ni1 = fma(-t, r0, i1);
   r0 = nr0; i0 = ni0; r1 = nr1; i1 = ni1;
 }
 
@@ -369,10 +410,11 @@ __device__ __forceinline__ double ipow(double x, int k) {
   return r;
 }
 
-template <int E>
-__device__ __forceinline__ void scale_tile(double (&vr)[E], double (&vi)[E], double f) {
+template <int E, class T>
+__device__ __forceinline__ void scale_tile(T (&vr)[E], T (&vi)[E], double f) {
+  const T ft = (T)f;
 #pragma unroll
-  for (int k = 0; k < E; ++k) { vr[k] *= f; vi[k] *= f; }
+  for (int k = 0; k < E; ++k) { vr[k] *= ft; vi[k] *= ft; }
 }
 
 
@@ -399,8 +441,8 @@ __device__ __forceinline__ uint32_t lds_tpart(uint32_t tid, int w) {
 // Window change wf -> wt through LDS.  Linear swizzle in bytes: per-thread
 // parts pf, pt (lds_tpart of the two windows), per-register part (g.loff,
 // already in bytes) from the host, so each access costs one XOR.
-template <class S, int EB>
-__device__ __forceinline__ void exchange_p(double (&vr)[1 << EB], double (&vi)[1 << EB], typename S::L* lds,
+template <class S, int EB, class T>
+__device__ __forceinline__ void exchange_p(T (&vr)[1 << EB], T (&vi)[1 << EB], typename S::L* lds,
                                            const TileGeom& g, int wf, int wt, uint32_t pf, uint32_t pt) {
   // a wave-local change writes and reads only the wave's own positions; the
   // positions it writes were last read by the same wave, so no barrier is
@@ -431,8 +473,8 @@ __device__ __forceinline__ void exchange_p(double (&vr)[1 << EB], double (&vi)[1
   }
 }
 
-template <class S, int EB>
-__device__ __forceinline__ void exchange_c(double (&vr)[1 << EB], double (&vi)[1 << EB], typename S::L* lds,
+template <class S, int EB, class T>
+__device__ __forceinline__ void exchange_c(T (&vr)[1 << EB], T (&vi)[1 << EB], typename S::L* lds,
                                            const TileGeom& g, uint32_t tid, int wf, int wt) {
   exchange_p<S, EB>(vr, vi, lds, g, wf, wt, lds_tpart<S, EB>(tid, wf), lds_tpart<S, EB>(tid, wt));
 }
@@ -447,9 +489,10 @@ __device__ __noinline__ double2 phase_direct(double g, double c) {
   return make_double2(cs, -sn);
 }
 
-__device__ __forceinline__ void cmul_inplace(double& r, double& i, double fr, double fi) {
-  const double nr = fma(fr, r, -fi * i);
-  const double ni = fma(fr, i, fi * r);
+template <class T>
+__device__ __forceinline__ void cmul_inplace(T& r, T& i, T fr, T fi) {
+  const T nr = fma(fr, r, -fi * i);
+  const T ni = fma(fr, i, fi * r);
   r = nr; i = ni;
 }
 
@@ -462,23 +505,29 @@ __device__ __forceinline__ void cmul_inplace(double& r, double& i, double fr, do
 //   byte decomposition).
 // One code path serves both cases, so the rare case costs no registers in the
 // common one; prepare_pass stages pass `pass`.
-__device__ __forceinline__ void prepare_pass(double2* tab, const double2* row, uint32_t tid, int pass) {
+// LDS table entry from a double2 table row (FP32 sweeps round it once here).
+__device__ __forceinline__ void tab_set(double2& d, const double2& s) { d = s; }
+__device__ __forceinline__ void tab_set(float2& d, const double2& s) { d = make_float2((float)s.x, (float)s.y); }
+
+template <class V>
+__device__ __forceinline__ void prepare_pass(V* tab, const double2* row, uint32_t tid, int pass) {
   __syncthreads();  // readers of the previous tables are done
-  for (uint32_t e = tid; e < 288u; e += blockDim.x) {
+  for (uint32_t e = tid; e < 288u; e += wg_size()) {
     if (pass == 0) {
-      if (e < 256u) tab[e] = row[288 + e];  // F1 (MID, LO stay)
+      if (e < 256u) tab_set(tab[e], row[288 + e]);  // F1 (MID, LO stay)
     } else {
-      tab[e] = row[544 + e];  // F3, F2M, F2L
+      tab_set(tab[e], row[544 + e]);  // F3, F2M, F2L
     }
   }
   __syncthreads();
 }
 
 // The phase factor of table index x (both cases above).
-__device__ __forceinline__ double2 table_phase(const double2* tab, uint32_t x) {
-  const double2 h = tab[(x >> 8) & 255u], m = tab[256u + ((x >> 4) & 15u)], l = tab[272u + (x & 15u)];
-  const double2 hm = make_double2(fma(h.x, m.x, -h.y * m.y), fma(h.x, m.y, h.y * m.x));
-  return make_double2(fma(hm.x, l.x, -hm.y * l.y), fma(hm.x, l.y, hm.y * l.x));
+template <class V>
+__device__ __forceinline__ V table_phase(const V* tab, uint32_t x) {
+  const V h = tab[(x >> 8) & 255u], m = tab[256u + ((x >> 4) & 15u)], l = tab[272u + (x & 15u)];
+  const V hm(fma(h.x, m.x, -h.y * m.y), fma(h.x, m.y, h.y * m.x));
+  return V(fma(hm.x, l.x, -hm.y * l.y), fma(hm.x, l.y, hm.y * l.x));
 }
 
 // Stage HI|LO and decide (workgroup-uniform) whether every value of the tile is
@@ -487,7 +536,7 @@ __device__ __forceinline__ double2 table_phase(const double2* tab, uint32_t x) {
 // written by each wave's first active lane, read by everyone after a barrier.
 __device__ __forceinline__ bool block_any(bool v, uint32_t* flags) {
   const uint64_t m = __ballot(v);
-  const uint32_t wv = threadIdx.x >> 6, nw = (blockDim.x + 63u) >> 6;
+  const uint32_t wv = threadIdx.x >> 6, nw = (wg_size() + 63u) >> 6;
   if (__lane_id() == (uint32_t)__ffsll((unsigned long long)__ballot(1)) - 1u) flags[wv] = m != 0;
   __syncthreads();
   uint32_t any = 0;
@@ -495,8 +544,8 @@ __device__ __forceinline__ bool block_any(bool v, uint32_t* flags) {
   return any != 0;
 }
 
-template <class D, int E, bool PRESTAGED = false>
-__device__ __forceinline__ bool stage_phase_tables(const typename D::RawT (&cv)[E], double2* tab, const double2* row,
+template <class D, int E, bool PRESTAGED = false, class V>
+__device__ __forceinline__ bool stage_phase_tables(const typename D::RawT (&cv)[E], V* tab, const double2* row,
                                                    uint32_t tid) {
   int ok = 1;
   if constexpr (!D::kAlwaysInTable) {
@@ -504,7 +553,7 @@ __device__ __forceinline__ bool stage_phase_tables(const typename D::RawT (&cv)[
     for (int k = 0; k < E; ++k) ok &= (D::tab_index(cv[k]) >= 0);
   }
   if constexpr (!PRESTAGED)  // else written at kernel start, overlapping the state loads
-    for (uint32_t e = tid; e < (uint32_t)kTabEntries; e += blockDim.x) tab[e] = row[e];
+    for (uint32_t e = tid; e < (uint32_t)kTabEntries; e += wg_size()) tab_set(tab[e], row[e]);
   if constexpr (D::kAlwaysInTable) {
     __syncthreads();
     return true;
@@ -518,10 +567,10 @@ __device__ __forceinline__ bool stage_phase_tables(const typename D::RawT (&cv)[
 // LDS-staged tables (one pass, or two byte-table passes when some int32 value
 // of the workgroup is outside the two-level table; a workgroup-uniform choice);
 // float64 ones evaluate sincos of the angle.
-template <class S, class D, int EB, bool PRESTAGED = false>
-__device__ __forceinline__ void phase_from_raw(double (&vr)[1 << EB], double (&vi)[1 << EB],
+template <class S, class D, int EB, bool PRESTAGED = false, class T, class V>
+__device__ __forceinline__ void phase_from_raw(T (&vr)[1 << EB], T (&vi)[1 << EB],
                                                const typename D::RawT (&cv)[1 << EB], const SweepArgs& a,
-                                               const LayerParams& lp, uint32_t tid, double2* tab) {
+                                               const LayerParams& lp, uint32_t tid, V* tab) {
   constexpr int E = 1 << EB;
   if constexpr (D::kTable) {
     const bool fast = stage_phase_tables<D, E, PRESTAGED>(cv, tab, lp.tab, tid);
@@ -537,7 +586,7 @@ __device__ __forceinline__ void phase_from_raw(double (&vr)[1 << EB], double (&v
       for (int k0 = 0; k0 < E; k0 += 4) {
 #pragma unroll
         for (int k = k0; k < k0 + 4 && k < E; ++k) {
-          const double2 f = table_phase(tab, ((uint32_t)cv[k] + add) >> shift);
+          const V f = table_phase(tab, ((uint32_t)cv[k] + add) >> shift);
           cmul_inplace(vr[k], vi[k], f.x, f.y);
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -547,7 +596,7 @@ __device__ __forceinline__ void phase_from_raw(double (&vr)[1 << EB], double (&v
 #pragma unroll
     for (int k = 0; k < E; ++k) {
       const double2 f = phase_direct(lp.g, D::value(cv[k]) + a.diag_offset);
-      cmul_inplace(vr[k], vi[k], f.x, f.y);
+      cmul_inplace(vr[k], vi[k], (T)f.x, (T)f.y);
     }
   }
 }
@@ -567,8 +616,8 @@ __device__ __forceinline__ void load_cost(typename D::RawT (&cv)[1 << EB], const
 }
 
 // Tangent-form butterflies on register bits [LO, HI) of the window.
-template <int EB, int LO, int HI>
-__device__ __forceinline__ void butterflies(double (&vr)[1 << EB], double (&vi)[1 << EB], double t) {
+template <int EB, int LO, int HI, class T>
+__device__ __forceinline__ void butterflies(T (&vr)[1 << EB], T (&vi)[1 << EB], T t) {
 #pragma unroll
   for (int j = LO; j < HI && j < EB; ++j) {
 #pragma unroll
@@ -582,7 +631,10 @@ __device__ __forceinline__ void butterflies(double (&vr)[1 << EB], double (&vi)[
 // chunk order or (REV) in reverse chunk order; the gates commute, so both
 // orders give the same layer.  Each gate is applied divided by cos(beta)
 // (rx_pair_t with tn = tan beta): the caller multiplies the tile by
-// cos(beta)^(tb - act_lo).  Returns the final window; pcur holds lds_tpart of
+// cos(beta)^(tb - act_lo), or (CS) each chunk is multiplied by cos(beta)^(its
+// gates) here, which keeps every window change's values at the scale of the
+// state: FP64 tiles whose exchanges go through FP32 LDS need that when
+// |tan beta| is large.  Returns the final window; pcur holds lds_tpart of
 // the current window on entry and on return (each change computes only the
 // new window's part).
 //
@@ -592,12 +644,14 @@ __device__ __forceinline__ void butterflies(double (&vr)[1 << EB], double (&vi)[
 // When PHI > PLO the caller guarantees that chunk g.part has jlo = PLO,
 // jhi = PHI; that chunk is then applied outside the loops with only its own
 // butterflies (plans have at most one such chunk of one to three bits).
-template <class S, int EB, bool REV = false, int PLO = 0, int PHI = 0>
-__device__ __forceinline__ int apply_mixer(double (&vr)[1 << EB], double (&vi)[1 << EB], typename S::L* lds,
-                                           const TileGeom& g, uint32_t tid, int w, double tn, uint32_t& pcur) {
+template <class S, int EB, bool REV = false, int PLO = 0, int PHI = 0, bool CS = false, class T>
+__device__ __forceinline__ int apply_mixer(T (&vr)[1 << EB], T (&vi)[1 << EB], typename S::L* lds,
+                                           const TileGeom& g, uint32_t tid, int w, double tn_d, double ca,
+                                           uint32_t& pcur) {
   constexpr int E = 1 << EB;
+  const T tn = (T)tn_d;
   constexpr bool kPart = PHI > PLO;
-  auto to_window = [&](int wt) {
+  auto to_window = [&](int wt) __attribute__((always_inline)) {
     if (wt != w) {
       const uint32_t pt = lds_tpart<S, EB>(tid, wt);
       exchange_p<S, EB>(vr, vi, lds, g, w, wt, pcur, pt);
@@ -605,16 +659,17 @@ __device__ __forceinline__ int apply_mixer(double (&vr)[1 << EB], double (&vi)[1
       pcur = pt;
     }
   };
-  auto chunk = [&](const Chunk ch) {
+  auto chunk = [&](const Chunk ch) __attribute__((always_inline)) {
     to_window(ch.w);
 #pragma unroll
     for (int j = 0; j < EB; ++j) {
-      const double tj = (j >= ch.jlo && j < ch.jhi) ? tn : 0.0;
+      const T tj = (j >= ch.jlo && j < ch.jhi) ? tn : T(0);
 #pragma unroll
       for (int k = 0; k < E; ++k) {
         if (!(k & (1 << j))) rx_pair_t(vr[k], vi[k], vr[k | (1 << j)], vi[k | (1 << j)], tj);
       }
     }
+    if constexpr (CS) scale_tile(vr, vi, ipow(ca, ch.jhi - ch.jlo));
   };
   const int nc = g.nchunks;
   if constexpr (!kPart) {
@@ -627,11 +682,13 @@ __device__ __forceinline__ int apply_mixer(double (&vr)[1 << EB], double (&vi)[1
       for (int i = 0; i < pi; ++i) chunk(g.chunk[i]);
       to_window(g.chunk[pi].w);
       butterflies<EB, PLO, PHI>(vr, vi, tn);
+      if constexpr (CS) scale_tile(vr, vi, ipow(ca, PHI - PLO));
       for (int i = pi + 1; i < nc; ++i) chunk(g.chunk[i]);
     } else {
       for (int i = nc - 1; i > pi; --i) chunk(g.chunk[i]);
       to_window(g.chunk[pi].w);
       butterflies<EB, PLO, PHI>(vr, vi, tn);
+      if constexpr (CS) scale_tile(vr, vi, ipow(ca, PHI - PLO));
       for (int i = pi - 1; i >= 0; --i) chunk(g.chunk[i]);
     }
   }
@@ -639,15 +696,16 @@ __device__ __forceinline__ int apply_mixer(double (&vr)[1 << EB], double (&vi)[1
 }
 
 // (E, norm) partial sums of the thread's elements.
-template <class D, int EB>
-__device__ __forceinline__ void expv_partials(const double (&vr)[1 << EB], const double (&vi)[1 << EB],
+template <class D, int EB, class T>
+__device__ __forceinline__ void expv_partials(const T (&vr)[1 << EB], const T (&vi)[1 << EB],
                                               const SweepArgs& a, uint64_t base, uint32_t tid, int w,
                                               double& e_part, double& n_part) {
   const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g);
 #pragma unroll
   for (int k = 0; k < (1 << EB); ++k) {
     const double c = D::get(a.diag, xb + a.g.goff[w][k]) + a.diag_offset;
-    const double pr = vr[k] * vr[k] + vi[k] * vi[k];
+    const double r = vr[k], i = vi[k];
+    const double pr = r * r + i * i;
     e_part += pr * c;
     n_part += pr;
   }
@@ -661,20 +719,13 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
   return (b & 7u) * (nb >> 3) + (b >> 3);
 }
 
-// One HBM sweep (multi-tile states).  The flags are compile-time so each
-// launch carries only the code it runs:
-//   INIT   generate |+> in registers instead of loading the state
-//   PHASE  apply the layer's phase before the mixer gates
-//   EXPV   emit per-workgroup (E, norm) partials of the result
-//   FUSE   the tile's mixer gates of layer l, the phase of layer l+1, then the
-//          tile's mixer gates of layer l+1 (valid when this sweep is the last
-//          of layer l: every other gate of layer l is already applied)
-template <class S, class D, int EB, bool INIT, bool PHASE, bool EXPV, bool FUSE, int PLO = 0, int PHI = 0>
-__global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_sweep_kernel(const SweepArgs a) {
+// The tile work of one sweep in arithmetic type R (table entries V).
+template <class S, class D, int EB, bool INIT, bool PHASE, bool EXPV, bool FUSE, int PLO, int PHI, class R, class V>
+__device__ __forceinline__ void sweep_tile(const SweepArgs& a) {
   constexpr int E = 1 << EB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   typename S::L* lds = reinterpret_cast<typename S::L*>(smem_raw);
-  double2* tab = reinterpret_cast<double2*>(smem_raw + (1u << a.g.tb) * S::kLdsBytes);
+  V* tab = reinterpret_cast<V*>(smem_raw + (1u << a.g.tb) * S::kLdsBytes);
   const uint32_t tid = threadIdx.x;
   const uint64_t base = block_base(xcd_block(blockIdx.x, gridDim.x), a.g);
   const uint32_t set = blockIdx.y;
@@ -687,7 +738,7 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
   constexpr bool kEarlyNext = FUSE && !S::kSplit;
   const LayerParams lq_early = kEarlyNext ? layer_params(a, set, 1) : lp;
 
-  double vr[E], vi[E];
+  R vr[E], vi[E];
   const int w_load = a.g.chunk[0].w;  // the load mapping: the first chunk's window
   int w = w_load;
   // EXPV: the cost values are read with the state, in the coalesced load
@@ -699,7 +750,7 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
     const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g);
     if constexpr (INIT) {
 #pragma unroll
-      for (int k = 0; k < E; ++k) { vr[k] = a.amp0; vi[k] = 0.0; }
+      for (int k = 0; k < E; ++k) { vr[k] = (R)a.amp0; vi[k] = R(0); }
     } else {
 #pragma unroll
       for (int k = 0; k < E; ++k) S::load(psi, xb + a.g.goff[w][k], vr[k], vi[k]);
@@ -726,7 +777,7 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
     // the tables of the phase this launch applies go to LDS now, overlapping
     // the state loads (FUSE: the next layer's; PHASE: this layer's)
     const LayerParams lq0 = FUSE ? (kEarlyNext ? lq_early : layer_params(a, set, 1)) : lp;
-    for (uint32_t e = tid; e < (uint32_t)kTabEntries; e += blockDim.x) tab[e] = lq0.tab[e];
+    for (uint32_t e = tid; e < (uint32_t)kTabEntries; e += wg_size()) tab_set(tab[e], lq0.tab[e]);
   }
   if constexpr (PHASE) {
     typename D::RawT pc[E];
@@ -734,9 +785,11 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
     phase_from_raw<S, D, EB, D::kTable>(vr, vi, pc, a, lp, tid, tab);
   }
   const int nq = a.g.tb - a.g.act_lo;  // gates per layer in this tile
+  // FP64 tiles of complex64 states (large |tan beta|) rescale chunk by chunk
+  constexpr bool kCS = S::kDualPrecision && std::is_same<R, double>::value;
   uint32_t pcur = lds_tpart<S, EB>(tid, w);
-  w = apply_mixer<S, EB, false, PLO, PHI>(vr, vi, lds, a.g, tid, w, lp.tn, pcur);
-  scale_tile(vr, vi, ipow(lp.ca, nq));
+  w = apply_mixer<S, EB, false, PLO, PHI, kCS>(vr, vi, lds, a.g, tid, w, lp.tn, lp.ca, pcur);
+  if constexpr (!kCS) scale_tile(vr, vi, ipow(lp.ca, nq));
   if constexpr (FUSE) {
     const LayerParams lq = kEarlyNext ? lq_early : layer_params(a, set, 1);
     if constexpr (kPackedCost) {
@@ -746,8 +799,8 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
       load_cost<D, EB>(cv, a, base, tid, w);
     }
     phase_from_raw<S, D, EB, D::kTable>(vr, vi, cv, a, lq, tid, tab);
-    w = apply_mixer<S, EB, true, PLO, PHI>(vr, vi, lds, a.g, tid, w, lq.tn, pcur);  // ends in the load mapping
-    scale_tile(vr, vi, ipow(lq.ca, nq));
+    w = apply_mixer<S, EB, true, PLO, PHI, kCS>(vr, vi, lds, a.g, tid, w, lq.tn, lq.ca, pcur);  // ends in the load mapping
+    if constexpr (!kCS) scale_tile(vr, vi, ipow(lq.ca, nq));
   }
 
   double e_part = 0.0, n_part = 0.0;
@@ -762,7 +815,8 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
   if constexpr (EXPV) {
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-      const double pr = vr[k] * vr[k] + vi[k] * vi[k];
+      const double r = vr[k], i = vi[k];
+      const double pr = r * r + i * i;
       e_part += pr * (D::value(cv[k]) + a.diag_offset);
       n_part += pr;
     }
@@ -780,6 +834,38 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
       part[2 * (uint64_t)blockIdx.x] = e_part;
       part[2 * (uint64_t)blockIdx.x + 1] = n_part;
     }
+  }
+}
+
+// One HBM sweep (multi-tile states).  The flags are compile-time so each
+// launch carries only the code it runs:
+//   INIT   generate |+> in registers instead of loading the state
+//   PHASE  apply the layer's phase before the mixer gates
+//   EXPV   emit per-workgroup (E, norm) partials of the result
+//   FUSE   the tile's mixer gates of layer l, the phase of layer l+1, then the
+//          tile's mixer gates of layer l+1 (valid when this sweep is the last
+//          of layer l: every other gate of layer l is already applied)
+// complex64 tiles compute in FP32 when every layer the launch applies has
+// |tan beta| <= kTanMaxF32, and in FP64 otherwise (a workgroup-uniform
+// choice): the tangent-form gates let the tile grow by 1/|cos beta| per gate
+// until the rescale after the layer's gates, at most 64.01^13 < 2^79 here,
+// far inside FP32's range, while beta near pi/2 would overflow it.
+template <class S, class D, int EB, bool INIT, bool PHASE, bool EXPV, bool FUSE, int PLO = 0, int PHI = 0>
+__global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_sweep_kernel(const SweepArgs a_param) {
+  if constexpr (S::kDualPrecision) {
+    // Two inlined tile bodies read the arguments where they lie, in the
+    // kernarg segment (the only explicit argument sits at its start): a
+    // reference to the by-value parameter made the compiler copy its 2.2 KiB
+    // into scratch memory per lane for them.
+    typedef __attribute__((address_space(4))) const SweepArgs KernArgs;
+    const SweepArgs& a = *(const SweepArgs*)(KernArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+    const uint32_t set = blockIdx.y;
+    bool f32 = fabs(layer_params(a, set, 0).tn) <= kTanMaxF32;
+    if constexpr (FUSE) f32 = f32 && fabs(layer_params(a, set, 1).tn) <= kTanMaxF32;
+    if (f32) sweep_tile<S, D, EB, INIT, PHASE, EXPV, FUSE, PLO, PHI, float, float2>(a);
+    else sweep_tile<S, D, EB, INIT, PHASE, EXPV, FUSE, PLO, PHI, double, double2>(a);
+  } else {
+    sweep_tile<S, D, EB, INIT, PHASE, EXPV, FUSE, PLO, PHI, typename S::R, typename S::Tab>(a_param);
   }
 }
 
@@ -812,9 +898,11 @@ __global__ void __launch_bounds__(512) qaoa_tile_kernel(const SweepArgs a) {
     phase_from_raw<S, D, EB>(vr, vi, pc, a, lp, tid, tab);
     // alternate the chunk order: each layer starts in the window the last one ended in
     uint32_t pcur = lds_tpart<S, EB>(tid, w);
-    if (l & 1) w = apply_mixer<S, EB, true>(vr, vi, lds, a.g, tid, w, lp.tn, pcur);
-    else w = apply_mixer<S, EB>(vr, vi, lds, a.g, tid, w, lp.tn, pcur);
-    scale_tile(vr, vi, ipow(lp.ca, a.g.tb));
+    // complex64 tiles exchange through FP32 LDS: rescale chunk by chunk
+    constexpr bool kCS = S::kDualPrecision;
+    if (l & 1) w = apply_mixer<S, EB, true, 0, 0, kCS>(vr, vi, lds, a.g, tid, w, lp.tn, lp.ca, pcur);
+    else w = apply_mixer<S, EB, false, 0, 0, kCS>(vr, vi, lds, a.g, tid, w, lp.tn, lp.ca, pcur);
+    if constexpr (!kCS) scale_tile(vr, vi, ipow(lp.ca, a.g.tb));
   }
   double e_part = 0.0, n_part = 0.0;
   if (a.flags & F_EXPV) expv_partials<D, EB>(vr, vi, a, 0, tid, w, e_part, n_part);
@@ -881,7 +969,7 @@ __device__ __forceinline__ int undo_mixer(double (&vr)[1 << EB], double (&vi)[1 
   const double c2 = ca * ca;
   // one chunk: register bits [lo, hi) of its window (compile-time bounds for
   // the specialised short chunk, so its other bits take no identity butterflies)
-  auto chunk = [&](const Chunk ch, auto lo_c, auto hi_c) {
+  auto chunk = [&](const Chunk ch, auto lo_c, auto hi_c) __attribute__((always_inline)) {
     constexpr int LO = decltype(lo_c)::value, HI = decltype(hi_c)::value;
     if (ch.w != w) {
       exchange_c<S, EB>(vr, vi, lds, g, tid, w, ch.w);

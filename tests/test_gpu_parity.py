@@ -266,6 +266,37 @@ def test_special_angles(q):
     del c
 
 
+# complex64 sweeps compute in FP32 while every layer a launch applies has
+# |tan beta| <= 64 and in FP64 otherwise (the tangent-form gates let a tile grow
+# by 1/|cos beta| per gate before its rescale).  Layers on both sides of the
+# bound, beta = pi/2 exactly, and fused launches that pair a large and a small
+# tangent; ragged 2^13-element tiles (n = 18, 21) in both cost dtypes, and the
+# single-tile kernel (n = 10), whose FP64 registers exchange through FP32 LDS.
+@pytest.mark.parametrize("n,ddt", [(10, "u16"), (18, "u16"), (21, "i32")])
+def test_complex64_precision_switch(q, n, ddt):
+    _say(f"complex64 precision switch n={n} {ddt}")
+    beta = [np.pi / 2, np.arctan(63.9), 0.3, np.pi / 2 - 1e-3, np.arctan(64.1), np.pi / 2 + 0.01, -np.arctan(63.9)]
+    gamma = list(np.linspace(0.05, 0.35, len(beta)))
+    if ddt == "u16":
+        terms, c = W.labs_terms(n), oracle.diag_labs(n).astype(np.float64)
+    else:
+        edges = W.random_regular_graph(4, n, seed=n)
+        weights = list(np.random.default_rng(n).integers(1, 11, size=len(edges)))
+        terms = W.maxcut_terms(edges, weights)
+        c = oracle.diag_maxcut(n, edges, weights)
+    diag, off = _c_of(q, n, terms, ddt)
+    psi, eo = _run(q, n, diag, off, gamma, beta, "complex64")
+    _compare(n, psi, eo, c, gamma, beta, "complex64")
+    # beta = pi/2 alone: the global bit flip times (-i)^n, in FP64 sweeps
+    rng = np.random.default_rng(n)
+    psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi0 = (psi0 / np.linalg.norm(psi0)).astype(np.complex64).astype(np.complex128)
+    zero_diag = torch.zeros(1 << n, dtype=torch.int32, device="cuda")
+    got, _ = _run(q, n, zero_diag, 0.0, [0.0], [np.pi / 2], "complex64", psi0=psi0)
+    N = 1 << n
+    assert np.max(np.abs(got - (-1j) ** n * psi0[np.arange(N) ^ (N - 1)])) < 1e-6
+
+
 def test_zero_weight_problem(q):
     n = 14
     diag, off = _c_of(q, n, [(0.0, (0, 1)), (0.0, (2, 5, 7))], "i32")
