@@ -1157,18 +1157,83 @@ __global__ void __launch_bounds__(512, S::kAdjMinWavesPerSimd) qaoa_adjoint_kern
 // ----------------------------------------------------------------------------
 constexpr int kMaxXyGates = 128;
 
-struct XyArgs {
-  SweepArgs s;       // state, cost vector, tables, geometry, parameter rows, partials, flags
-  int ngates;        // gates per layer in this launch, applied in order
-  int dicke_k;       // F_INIT: -1 = |+>^n (amp0 everywhere); k >= 0 = amp0 on Hamming weight k
-  int8_t gate[kMaxXyGates][2];  // tile-bit pairs (i, j)
-};
-
 // x with zero bits inserted at positions lo < hi.
 __device__ __forceinline__ uint32_t insert_two_zeros(uint32_t q, int lo, int hi) {
   q = ((q >> lo) << (lo + 1)) | (q & ((1u << lo) - 1u));
   return ((q >> hi) << (hi + 1)) | (q & ((1u << hi) - 1u));
 }
+
+struct XyArgs {
+  SweepArgs s;       // state, cost vector, tables, geometry, parameter rows, partials, flags
+  int ngates;        // gates per layer in this launch, applied in order
+  int dicke_k;       // F_INIT: -1 = |+>^n (amp0 everywhere); k >= 0 = amp0 on Hamming weight k
+  int ngroups;       // > 0: the gates in ngroups groups of consecutive gates (below), else one pass per gate
+  int8_t gate[kMaxXyGates][2];  // tile-bit pairs (i, j)
+  // Group g is one LDS pass over the next gates of the list, of kind
+  //   XG_ONE   one gate, on its two amplitudes per pair (gate[e])
+  //   XG_PAIR  two gates on disjoint qubits: local bits (0,1), (2,3)
+  //   XG_STAR2 two gates sharing local bit 0: (0,1) then (0,2)
+  //   XG_STAR3 three gates sharing local bit 0: (0,1), (0,2), (0,3)
+  // over tile bits grp_bits[g] (local bit order; a fourth bit pads STAR2)
+  // and the same bits ascending in grp_sorted[g].
+  int8_t grp_kind[kMaxXyGates];
+  int8_t grp_bits[kMaxXyGates][4];
+  int8_t grp_sorted[kMaxXyGates][4];
+};
+enum : int { XG_ONE = 1, XG_PAIR = 2, XG_STAR2 = 3, XG_STAR3 = 4 };
+
+// LDS position of XY tile entry t (16-byte entries): the low four bits are
+// XORed with bits 4-7 and 8-11, so 16 consecutive lanes reach 16 different
+// 16-byte slots of a 256-byte bank row for the usual access patterns (whole
+// tile in order, gate pairs, four-bit groups at any bits).
+__device__ __forceinline__ uint32_t xy_pos(uint32_t t) { return t ^ (((t >> 4) ^ (t >> 8)) & 15u); }
+
+// One XY gate on local bits (I, J) of a 16-amplitude group in registers:
+// amplitudes with (bit I, bit J) = (0, 1) and (1, 0) are rotated together.
+template <int I, int J>
+__device__ __forceinline__ void xy_gate16(double (&r)[16], double (&m)[16], double ca, double sb) {
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (((k >> I) & 1) == 0 && ((k >> J) & 1) == 1) {
+      const int k1 = k ^ (1 << I) ^ (1 << J);
+      rx_pair(r[k], m[k], r[k1], m[k1], ca, sb);
+    }
+  }
+}
+
+// One grouped LDS pass of kind KIND (XG_PAIR / XG_STAR2 / XG_STAR3): each
+// work item loads the 16 amplitudes of one value of the other tile bits,
+// applies the kind's gates in order and writes them back.  Tile position of
+// local index k: the item's part xor the uniform part of k's bits (xy_pos is
+// linear over GF(2)).
+template <int KIND>
+__device__ __forceinline__ void xy_group_pass(double2* tile, const int8_t (&lb)[4], const int8_t (&sb4)[4],
+                                              uint32_t tid, uint32_t nitems, double ca, double sb) {
+  const int b0 = lb[0], b1 = lb[1], b2 = lb[2], b3 = lb[3];
+  for (uint32_t q = tid; q < nitems; q += wg_size()) {
+    const uint32_t px = xy_pos(insert_two_zeros(insert_two_zeros(q, sb4[0], sb4[1]), sb4[2], sb4[3]));
+    double r[16], m[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const double2 v = tile[px ^ xy_pos(((uint32_t)(k & 1) << b0) | ((uint32_t)((k >> 1) & 1) << b1) |
+                                         ((uint32_t)((k >> 2) & 1) << b2) | ((uint32_t)((k >> 3) & 1) << b3))];
+      r[k] = v.x; m[k] = v.y;
+    }
+    if constexpr (KIND == XG_PAIR) {
+      xy_gate16<0, 1>(r, m, ca, sb);
+      xy_gate16<2, 3>(r, m, ca, sb);
+    } else {
+      xy_gate16<0, 1>(r, m, ca, sb);
+      xy_gate16<0, 2>(r, m, ca, sb);
+      if constexpr (KIND == XG_STAR3) xy_gate16<0, 3>(r, m, ca, sb);
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      tile[px ^ xy_pos(((uint32_t)(k & 1) << b0) | ((uint32_t)((k >> 1) & 1) << b1) |
+                       ((uint32_t)((k >> 2) & 1) << b2) | ((uint32_t)((k >> 3) & 1) << b3))] = make_double2(r[k], m[k]);
+  }
+}
+
 
 // One launch: for each of nlayers layers (several only when the tile is the
 // whole state): [phase] then the gate list; flags F_INIT / F_PHASE / F_EXPV as
@@ -1203,38 +1268,73 @@ __global__ void __launch_bounds__(512) qaoa_xy_kernel(const XyArgs a) {
   typename D::RawT cv[E];
   if (sa.flags & (F_PHASE | F_EXPV)) load_cost<D, EB>(cv, sa, base, tid, w);
   const uint32_t npairs = 1u << (g.tb - 2);
+  // xy_pos is linear over GF(2): the position of thr | k << w (disjoint bits)
+  // is xy_pos(thr) ^ xy_pos(k << w), a per-thread part and a uniform part
+  const uint32_t pthr = xy_pos(thr_part<EB>(tid, w));
   for (int l = 0; l < sa.nlayers; ++l) {
     const LayerParams lp = layer_params(sa, set, l);
     if (l > 0) {
 #pragma unroll
       for (int k = 0; k < E; ++k) {
-        const double2 v = tile[tmap<EB>(tid, k, w)];
+        const double2 v = tile[pthr ^ xy_pos((uint32_t)k << w)];
         vr[k] = v.x; vi[k] = v.y;
       }
       __syncthreads();  // table reads of the previous layer are done before restaging
     }
     if (sa.flags & F_PHASE) phase_from_raw<S, D, EB>(vr, vi, cv, sa, lp, tid, tab);
 #pragma unroll
-    for (int k = 0; k < E; ++k) tile[tmap<EB>(tid, k, w)] = make_double2(vr[k], vi[k]);
+    for (int k = 0; k < E; ++k) tile[pthr ^ xy_pos((uint32_t)k << w)] = make_double2(vr[k], vi[k]);
     __syncthreads();
-    for (int e = 0; e < a.ngates; ++e) {
-      const int ti = a.gate[e][0], tj = a.gate[e][1];
-      const int lo = ti < tj ? ti : tj, hi = ti < tj ? tj : ti;
-      for (uint32_t q = tid; q < npairs; q += blockDim.x) {
-        const uint32_t x = insert_two_zeros(q, lo, hi);
-        const uint32_t x0 = x | (1u << tj), x1 = x | (1u << ti);
-        double2 u = tile[x0], v = tile[x1];
-        rx_pair(u.x, u.y, v.x, v.y, lp.ca, lp.sb);
-        tile[x0] = u;
-        tile[x1] = v;
+    if (a.ngroups > 0) {
+      // gates in groups: one LDS pass and one barrier per group
+      const uint32_t nitems = 1u << (g.tb - 4);
+      int e = 0;
+      for (int gi = 0; gi < a.ngroups; ++gi) {
+        const int kind = a.grp_kind[gi];
+        if (kind == XG_ONE) {
+          const int ti = a.gate[e][0], tj = a.gate[e][1];
+          const int lo = ti < tj ? ti : tj, hi = ti < tj ? tj : ti;
+          for (uint32_t q = tid; q < npairs; q += blockDim.x) {
+            const uint32_t x = insert_two_zeros(q, lo, hi);
+            const uint32_t x0 = xy_pos(x | (1u << tj)), x1 = xy_pos(x | (1u << ti));
+            double2 u = tile[x0], v = tile[x1];
+            rx_pair(u.x, u.y, v.x, v.y, lp.ca, lp.sb);
+            tile[x0] = u;
+            tile[x1] = v;
+          }
+          e += 1;
+        } else if (kind == XG_PAIR) {
+          xy_group_pass<XG_PAIR>(tile, a.grp_bits[gi], a.grp_sorted[gi], tid, nitems, lp.ca, lp.sb);
+          e += 2;
+        } else if (kind == XG_STAR2) {
+          xy_group_pass<XG_STAR2>(tile, a.grp_bits[gi], a.grp_sorted[gi], tid, nitems, lp.ca, lp.sb);
+          e += 2;
+        } else {
+          xy_group_pass<XG_STAR3>(tile, a.grp_bits[gi], a.grp_sorted[gi], tid, nitems, lp.ca, lp.sb);
+          e += 3;
+        }
+        __syncthreads();
       }
-      __syncthreads();
+    } else {
+      for (int e = 0; e < a.ngates; ++e) {
+        const int ti = a.gate[e][0], tj = a.gate[e][1];
+        const int lo = ti < tj ? ti : tj, hi = ti < tj ? tj : ti;
+        for (uint32_t q = tid; q < npairs; q += blockDim.x) {
+          const uint32_t x = insert_two_zeros(q, lo, hi);
+          const uint32_t x0 = xy_pos(x | (1u << tj)), x1 = xy_pos(x | (1u << ti));
+          double2 u = tile[x0], v = tile[x1];
+          rx_pair(u.x, u.y, v.x, v.y, lp.ca, lp.sb);
+          tile[x0] = u;
+          tile[x1] = v;
+        }
+        __syncthreads();
+      }
     }
   }
   if (sa.nlayers > 0) {  // else the registers still hold the loaded (or generated) state
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-      const double2 v = tile[tmap<EB>(tid, k, w)];
+      const double2 v = tile[pthr ^ xy_pos((uint32_t)k << w)];
       vr[k] = v.x; vi[k] = v.y;
     }
   }

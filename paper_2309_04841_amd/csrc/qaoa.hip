@@ -604,6 +604,63 @@ void launch_tile(const qk::SweepArgs& a, int state_dtype, int diag_dtype, int eb
   else launch_tile_s<qk::C64>(a, diag_dtype, eb, sets, st);
 }
 
+// Consecutive gates of a sweep share one LDS pass when they form one of the
+// kernel's group kinds: two gates on disjoint qubits (XG_PAIR), or two or
+// three gates with one common qubit and distinct others (XG_STAR2, XG_STAR3,
+// applied in list order); any other gate is a pass of its own (XG_ONE).  A
+// group's tile bits are listed in the kind's local order (the common qubit
+// first), STAR2 padded with the lowest tile bit it does not use.  Kernels with
+// fewer than four register bits per thread (the smallest states) keep one pass
+// per gate (ngroups = 0).
+void set_xy_groups(qk::XyArgs& a, int tb, int eb) {
+  a.ngroups = 0;
+  if (eb != 4 || tb < 4 || a.ngates == 0) return;
+  auto g0 = [&](int e) { return (int)a.gate[e][0]; };
+  auto g1 = [&](int e) { return (int)a.gate[e][1]; };
+  int e = 0;
+  while (e < a.ngates) {
+    const int gi = a.ngroups++;
+    int bits[4] = {g0(e), g1(e), -1, -1};
+    int kind = qk::XG_ONE, used = 1;
+    if (e + 1 < a.ngates) {
+      const int c = g0(e + 1), d = g1(e + 1);
+      const bool sc = c == bits[0] || c == bits[1], sd = d == bits[0] || d == bits[1];
+      if (!sc && !sd) {
+        kind = qk::XG_PAIR; used = 2;
+        bits[2] = c; bits[3] = d;
+      } else if (sc != sd) {
+        const int center = sc ? c : d, other = sc ? d : c;
+        const int first = bits[0] == center ? bits[1] : bits[0];
+        bits[0] = center; bits[1] = first; bits[2] = other;
+        kind = qk::XG_STAR2; used = 2;
+        if (e + 2 < a.ngates) {
+          const int x = g0(e + 2), y = g1(e + 2);
+          const int nx = x == center ? y : (y == center ? x : -1);
+          if (nx >= 0 && nx != first && nx != other) {
+            bits[3] = nx;
+            kind = qk::XG_STAR3; used = 3;
+          }
+        }
+        if (kind == qk::XG_STAR2)
+          for (int b = 0; b < tb; ++b)
+            if (b != bits[0] && b != bits[1] && b != bits[2]) { bits[3] = b; break; }
+      }
+    }
+    a.grp_kind[gi] = (int8_t)kind;
+    if (kind != qk::XG_ONE) {
+      int srt[4] = {bits[0], bits[1], bits[2], bits[3]};
+      std::sort(srt, srt + 4);
+      for (int i = 0; i < 4; ++i) {
+        a.grp_bits[gi][i] = (int8_t)bits[i];
+        a.grp_sorted[gi][i] = (int8_t)srt[i];
+      }
+    }
+    e += used;
+  }
+}
+
+static_assert(sizeof(qk::XyArgs) <= 4096, "XY launch arguments exceed the kernarg limit");
+
 // XY mixer launches: tile of 2^tb complex128 LDS entries + phase tables + flags.
 template <class S, class D, int EB>
 void launch_xy_t(const qk::XyArgs& a, uint64_t blocks, uint32_t sets, hipStream_t st) {
@@ -1526,6 +1583,7 @@ int qaoa_evolve_xy(int n, int p, const double* gamma, const double* beta, int mi
       a.gate[e][0] = (int8_t)sw.gates[e].first;
       a.gate[e][1] = (int8_t)sw.gates[e].second;
     }
+    set_xy_groups(a, sw.g.tb, pl.eb);
   };
   if (p == 0) {  // the initial state only (and its objective)
     a.s.g = pl.sweeps[0].g;
