@@ -298,28 +298,22 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Threads per workgroup, read from the dispatch packet (workgroup_size_x, bytes
-// 4-5) with a scalar load.  blockDim.x inside an inlined helper becomes a
-// per-lane load that allows for a partial last workgroup, and its wait for
-// vector memory (vmcnt(0)) would stall on the tile's state loads in flight;
-// every launch here has whole workgroups.
-__device__ __forceinline__ uint32_t wg_size() {
-  typedef __attribute__((address_space(4))) const uint16_t packet_u16;
-  return ((packet_u16*)__builtin_amdgcn_dispatch_ptr())[2];
-}
-
 // Sums (x, y) over the workgroup in a fixed order; result valid in thread 0.
 // `scratch` holds 2 doubles per wave (2 per thread when the workgroup is a
 // single partial wave).  Ends with all threads past a barrier.
-__device__ __forceinline__ void block_sum2(double& x, double& y, double* scratch) {
-  if (wg_size() < 64) {
+// nthr: threads of the workgroup, passed in by each kernel (blockDim.x read
+// in the kernel body, or the tile geometry): blockDim.x inside an inlined
+// helper becomes a per-lane load that allows for a partial last workgroup and
+// waits for all vector memory (vmcnt(0)), stalling on loads in flight.
+__device__ __forceinline__ void block_sum2(double& x, double& y, double* scratch, uint32_t nthr) {
+  if (nthr < 64) {
     // partial wave: no cross-lane shuffles over inactive lanes
     scratch[2 * threadIdx.x] = x;
     scratch[2 * threadIdx.x + 1] = y;
     __syncthreads();
     if (threadIdx.x == 0) {
       double sx = 0.0, sy = 0.0;
-      for (uint32_t i = 0; i < wg_size(); ++i) { sx += scratch[2 * i]; sy += scratch[2 * i + 1]; }
+      for (uint32_t i = 0; i < nthr; ++i) { sx += scratch[2 * i]; sy += scratch[2 * i + 1]; }
       x = sx; y = sy;
     }
     __syncthreads();
@@ -331,7 +325,7 @@ __device__ __forceinline__ void block_sum2(double& x, double& y, double* scratch
   if (lane == 0) { scratch[2 * wv] = x; scratch[2 * wv + 1] = y; }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t nw = (wg_size() + 63u) >> 6;
+    const uint32_t nw = (nthr + 63u) >> 6;
     double sx = 0.0, sy = 0.0;
     for (uint32_t i = 0; i < nw; ++i) { sx += scratch[2 * i]; sy += scratch[2 * i + 1]; }
     x = sx; y = sy;
@@ -514,9 +508,9 @@ __device__ __forceinline__ void tab_set(double2& d, const double2& s) { d = s; }
 __device__ __forceinline__ void tab_set(float2& d, const double2& s) { d = make_float2((float)s.x, (float)s.y); }
 
 template <class V>
-__device__ __forceinline__ void prepare_pass(V* tab, const double2* row, uint32_t tid, int pass) {
+__device__ __forceinline__ void prepare_pass(V* tab, const double2* row, uint32_t tid, int pass, uint32_t nthr) {
   __syncthreads();  // readers of the previous tables are done
-  for (uint32_t e = tid; e < 288u; e += wg_size()) {
+  for (uint32_t e = tid; e < 288u; e += nthr) {
     if (pass == 0) {
       if (e < 256u) tab_set(tab[e], row[288 + e]);  // F1 (MID, LO stay)
     } else {
@@ -538,9 +532,9 @@ __device__ __forceinline__ V table_phase(const V* tab, uint32_t x) {
 // covered by it.
 // Workgroup-wide OR of a flag: one word per wave after the tables (flags),
 // written by each wave's first active lane, read by everyone after a barrier.
-__device__ __forceinline__ bool block_any(bool v, uint32_t* flags) {
+__device__ __forceinline__ bool block_any(bool v, uint32_t* flags, uint32_t nthr) {
   const uint64_t m = __ballot(v);
-  const uint32_t wv = threadIdx.x >> 6, nw = (wg_size() + 63u) >> 6;
+  const uint32_t wv = threadIdx.x >> 6, nw = (nthr + 63u) >> 6;
   if (__lane_id() == (uint32_t)__ffsll((unsigned long long)__ballot(1)) - 1u) flags[wv] = m != 0;
   __syncthreads();
   uint32_t any = 0;
@@ -550,19 +544,19 @@ __device__ __forceinline__ bool block_any(bool v, uint32_t* flags) {
 
 template <class D, int E, bool PRESTAGED = false, class V>
 __device__ __forceinline__ bool stage_phase_tables(const typename D::RawT (&cv)[E], V* tab, const double2* row,
-                                                   uint32_t tid) {
+                                                   uint32_t tid, uint32_t nthr) {
   int ok = 1;
   if constexpr (!D::kAlwaysInTable) {
 #pragma unroll
     for (int k = 0; k < E; ++k) ok &= (D::tab_index(cv[k]) >= 0);
   }
   if constexpr (!PRESTAGED)  // else written at kernel start, overlapping the state loads
-    for (uint32_t e = tid; e < (uint32_t)kTabEntries; e += wg_size()) tab_set(tab[e], row[e]);
+    for (uint32_t e = tid; e < (uint32_t)kTabEntries; e += nthr) tab_set(tab[e], row[e]);
   if constexpr (D::kAlwaysInTable) {
     __syncthreads();
     return true;
   } else {
-    return !block_any(!ok, reinterpret_cast<uint32_t*>(tab + kTabEntries));
+    return !block_any(!ok, reinterpret_cast<uint32_t*>(tab + kTabEntries), nthr);
   }
 }
 
@@ -574,15 +568,15 @@ __device__ __forceinline__ bool stage_phase_tables(const typename D::RawT (&cv)[
 template <class S, class D, int EB, bool PRESTAGED = false, class T, class V>
 __device__ __forceinline__ void phase_from_raw(T (&vr)[1 << EB], T (&vi)[1 << EB],
                                                const typename D::RawT (&cv)[1 << EB], const SweepArgs& a,
-                                               const LayerParams& lp, uint32_t tid, V* tab) {
+                                               const LayerParams& lp, uint32_t tid, V* tab, uint32_t nthr) {
   constexpr int E = 1 << EB;
   if constexpr (D::kTable) {
-    const bool fast = stage_phase_tables<D, E, PRESTAGED>(cv, tab, lp.tab, tid);
+    const bool fast = stage_phase_tables<D, E, PRESTAGED>(cv, tab, lp.tab, tid, nthr);
     const int npass = fast ? 1 : 2;
     const uint32_t add = fast ? (uint32_t)(-(int32_t)D::kTableBase) : 0u;
 #pragma clang loop unroll(disable)
     for (int pass = 0; pass < npass; ++pass) {
-      if (!fast) prepare_pass(tab, lp.tab, tid, pass);
+      if (!fast) prepare_pass(tab, lp.tab, tid, pass, nthr);
       const int shift = pass ? 16 : 0;
       // groups of four elements: bounds how many table entries the scheduler
       // keeps in flight (register pressure decides occupancy here)
@@ -731,6 +725,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a) {
   typename S::L* lds = reinterpret_cast<typename S::L*>(smem_raw);
   V* tab = reinterpret_cast<V*>(smem_raw + (1u << a.g.tb) * S::kLdsBytes);
   const uint32_t tid = threadIdx.x;
+  const uint32_t nthr = 1u << (a.g.tb - EB);  // the launch's threads per workgroup
   const uint64_t base = block_base(xcd_block(blockIdx.x, gridDim.x), a.g);
   const uint32_t set = blockIdx.y;
   void* psi = reinterpret_cast<char*>(a.psi) + (uint64_t)set * a.set_stride_bytes;
@@ -781,12 +776,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a) {
     // the tables of the phase this launch applies go to LDS now, overlapping
     // the state loads (FUSE: the next layer's; PHASE: this layer's)
     const LayerParams lq0 = FUSE ? (kEarlyNext ? lq_early : layer_params(a, set, 1)) : lp;
-    for (uint32_t e = tid; e < (uint32_t)kTabEntries; e += wg_size()) tab_set(tab[e], lq0.tab[e]);
+    for (uint32_t e = tid; e < (uint32_t)kTabEntries; e += nthr) tab_set(tab[e], lq0.tab[e]);
   }
   if constexpr (PHASE) {
     typename D::RawT pc[E];
     load_cost<D, EB>(pc, a, base, tid, w);
-    phase_from_raw<S, D, EB, D::kTable>(vr, vi, pc, a, lp, tid, tab);
+    phase_from_raw<S, D, EB, D::kTable>(vr, vi, pc, a, lp, tid, tab, nthr);
   }
   const int nq = a.g.tb - a.g.act_lo;  // gates per layer in this tile
   // FP64 tiles of complex64 states (large |tan beta|) rescale chunk by chunk
@@ -802,7 +797,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a) {
     } else if constexpr (!kEarlyCost) {
       load_cost<D, EB>(cv, a, base, tid, w);
     }
-    phase_from_raw<S, D, EB, D::kTable>(vr, vi, cv, a, lq, tid, tab);
+    phase_from_raw<S, D, EB, D::kTable>(vr, vi, cv, a, lq, tid, tab, nthr);
     w = apply_mixer<S, EB, true, PLO, PHI, kCS>(vr, vi, lds, a.g, tid, w, lq.tn, lq.ca, pcur);  // ends in the load mapping
     if constexpr (!kCS) scale_tile(vr, vi, ipow(lq.ca, nq));
   }
@@ -832,7 +827,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a) {
   }
   if constexpr (EXPV) {
     __syncthreads();  // the tile buffer becomes reduction scratch (the last window change may have been wave-local)
-    block_sum2(e_part, n_part, reinterpret_cast<double*>(smem_raw));
+    block_sum2(e_part, n_part, reinterpret_cast<double*>(smem_raw), nthr);
     if (tid == 0) {
       double* part = a.partials + (uint64_t)set * a.partials_stride;
       part[2 * (uint64_t)blockIdx.x] = e_part;
@@ -880,6 +875,7 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
 // in one launch, one workgroup.  Latency-bound; runtime flags.
 template <class S, class D, int EB>
 __global__ void __launch_bounds__(512) qaoa_tile_kernel(const SweepArgs a) {
+  const uint32_t nthr = blockDim.x;
   constexpr int E = 1 << EB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   typename S::L* lds = reinterpret_cast<typename S::L*>(smem_raw);
@@ -902,7 +898,7 @@ __global__ void __launch_bounds__(512) qaoa_tile_kernel(const SweepArgs a) {
     const LayerParams lp = layer_params(a, set, l);
     typename D::RawT pc[E];
     load_cost<D, EB>(pc, a, 0, tid, w);
-    phase_from_raw<S, D, EB>(vr, vi, pc, a, lp, tid, tab);
+    phase_from_raw<S, D, EB>(vr, vi, pc, a, lp, tid, tab, nthr);
     // alternate the chunk order: each layer starts in the window the last one ended in
     uint32_t pcur = lds_tpart<S, EB>(tid, w);
     // complex64 tiles exchange through FP32 LDS: rescale chunk by chunk
@@ -921,7 +917,7 @@ __global__ void __launch_bounds__(512) qaoa_tile_kernel(const SweepArgs a) {
   for (int k = 0; k < E; ++k) S::store(psi, tmap<EB>(tid, k, w), vr[k], vi[k]);
   if (a.flags & F_EXPV) {
     __syncthreads();  // the tile buffer becomes reduction scratch
-    block_sum2(e_part, n_part, reinterpret_cast<double*>(smem_raw));
+    block_sum2(e_part, n_part, reinterpret_cast<double*>(smem_raw), nthr);
     if (tid == 0) {
       double* part = a.partials + (uint64_t)set * a.partials_stride;
       part[0] = e_part;
@@ -1033,17 +1029,17 @@ template <class D, int EB>
 __device__ __forceinline__ void undo_phase(double (&vr)[1 << EB], double (&vi)[1 << EB], double (&lr)[1 << EB],
                                            double (&li)[1 << EB], const typename D::RawT (&cv)[1 << EB],
                                            const AdjArgs& a, const LayerParams& lp, double2* tab, uint32_t tid,
-                                           double& gacc) {
+                                           double& gacc, uint32_t nthr) {
   constexpr int E = 1 << EB;
 #pragma unroll
   for (int k = 0; k < E; ++k) gacc += (D::value(cv[k]) + a.diag_offset) * (lr[k] * vi[k] - li[k] * vr[k]);
   if constexpr (D::kTable) {
-    const bool fast = stage_phase_tables<D, E>(cv, tab, lp.tab, tid);
+    const bool fast = stage_phase_tables<D, E>(cv, tab, lp.tab, tid, nthr);
     const int npass = fast ? 1 : 2;
     const uint32_t add = fast ? (uint32_t)(-(int32_t)D::kTableBase) : 0u;
 #pragma clang loop unroll(disable)
     for (int pass = 0; pass < npass; ++pass) {
-      if (!fast) prepare_pass(tab, lp.tab, tid, pass);
+      if (!fast) prepare_pass(tab, lp.tab, tid, pass, nthr);
       const int shift = pass ? 16 : 0;
 #pragma unroll
       for (int k0 = 0; k0 < E; k0 += 4) {
@@ -1080,6 +1076,7 @@ __device__ __forceinline__ void undo_phase(double (&vr)[1 << EB], double (&vi)[1
 // launch by a third, and the gradient gained only 2.6 %.
 template <class S, class D, int EB, bool FIRST, bool PHASE, bool FUSE, int PLO = 0, int PHI = 0>
 __global__ void __launch_bounds__(512, S::kAdjMinWavesPerSimd) qaoa_adjoint_kernel(const AdjArgs a) {
+  const uint32_t nthr = blockDim.x;
   constexpr int E = 1 << EB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   typename S::L* lds = reinterpret_cast<typename S::L*>(smem_raw);
@@ -1116,7 +1113,7 @@ __global__ void __launch_bounds__(512, S::kAdjMinWavesPerSimd) qaoa_adjoint_kern
   double xacc = 0.0, gacc = 0.0, xacc2 = 0.0;
   w = undo_mixer<S, EB, false, PLO, PHI>(vr, vi, lr, li, lds, a.g, tid, w, lp.ca, lp.tn, xacc);
   if constexpr (FUSE) {
-    undo_phase<D, EB>(vr, vi, lr, li, cv, a, lp, tab, tid, gacc);
+    undo_phase<D, EB>(vr, vi, lr, li, cv, a, lp, tab, tid, gacc, nthr);
     const size_t r1 = r - 1;
     w = undo_mixer<S, EB, true, PLO, PHI>(vr, vi, lr, li, lds, a.g, tid, w, a.pset[kParamRow * r1 + 1],
                                           a.pset[kParamRow * r1 + 3], xacc2);
@@ -1127,7 +1124,7 @@ __global__ void __launch_bounds__(512, S::kAdjMinWavesPerSimd) qaoa_adjoint_kern
     exchange_c<S, EB>(lr, li, lds, a.g, tid, w, w_out);
     w = w_out;
   }
-  if constexpr (PHASE) undo_phase<D, EB>(vr, vi, lr, li, cv, a, lp, tab, tid, gacc);
+  if constexpr (PHASE) undo_phase<D, EB>(vr, vi, lr, li, cv, a, lp, tab, tid, gacc, nthr);
   {
     const uint64_t xb = base + tile_off(thr_part<EB>(tid, w), a.g);
 #pragma unroll
@@ -1138,14 +1135,14 @@ __global__ void __launch_bounds__(512, S::kAdjMinWavesPerSimd) qaoa_adjoint_kern
     }
   }
   __syncthreads();  // the tables and tile buffer are reused as reduction scratch
-  block_sum2(xacc, gacc, reinterpret_cast<double*>(smem_raw));
+  block_sum2(xacc, gacc, reinterpret_cast<double*>(smem_raw), nthr);
   if (tid == 0) {
     a.partials[2 * (uint64_t)blockIdx.x] = xacc;
     a.partials[2 * (uint64_t)blockIdx.x + 1] = gacc;
   }
   if constexpr (FUSE) {
     double zero = 0.0;
-    block_sum2(xacc2, zero, reinterpret_cast<double*>(smem_raw));
+    block_sum2(xacc2, zero, reinterpret_cast<double*>(smem_raw), nthr);
     if (tid == 0) {
       a.partials2[2 * (uint64_t)blockIdx.x] = xacc2;
       a.partials2[2 * (uint64_t)blockIdx.x + 1] = 0.0;
@@ -1215,9 +1212,9 @@ __device__ __forceinline__ void xy_gate16(double (&r)[16], double (&m)[16], doub
 // linear over GF(2)).
 template <int KIND>
 __device__ __forceinline__ void xy_group_pass(double2* tile, const int8_t (&lb)[4], const int8_t (&sb4)[4],
-                                              uint32_t tid, uint32_t nitems, double ca, double sb) {
+                                              uint32_t tid, uint32_t nitems, double ca, double sb, uint32_t nthr) {
   const int b0 = lb[0], b1 = lb[1], b2 = lb[2], b3 = lb[3];
-  for (uint32_t q = tid; q < nitems; q += wg_size()) {
+  for (uint32_t q = tid; q < nitems; q += nthr) {
     const uint32_t px = xy_pos(insert_two_zeros(insert_two_zeros(q, sb4[0], sb4[1]), sb4[2], sb4[3]));
     double r[16], m[16];
 #pragma unroll
@@ -1247,6 +1244,7 @@ __device__ __forceinline__ void xy_group_pass(double2* tile, const int8_t (&lb)[
 // in the X mixer sweeps.  Tile in LDS as double2, 2^tb entries, natural order.
 template <class S, class D, int EB>
 __global__ void __launch_bounds__(512) qaoa_xy_kernel(const XyArgs a) {
+  const uint32_t nthr = blockDim.x;
   constexpr int E = 1 << EB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const SweepArgs& sa = a.s;
@@ -1288,7 +1286,7 @@ __global__ void __launch_bounds__(512) qaoa_xy_kernel(const XyArgs a) {
       }
       __syncthreads();  // table reads of the previous layer are done before restaging
     }
-    if (sa.flags & F_PHASE) phase_from_raw<S, D, EB>(vr, vi, cv, sa, lp, tid, tab);
+    if (sa.flags & F_PHASE) phase_from_raw<S, D, EB>(vr, vi, cv, sa, lp, tid, tab, nthr);
 #pragma unroll
     for (int k = 0; k < E; ++k) tile[pthr ^ xy_pos((uint32_t)k << w)] = make_double2(vr[k], vi[k]);
     __syncthreads();
@@ -1311,13 +1309,13 @@ __global__ void __launch_bounds__(512) qaoa_xy_kernel(const XyArgs a) {
           }
           e += 1;
         } else if (kind == XG_PAIR) {
-          xy_group_pass<XG_PAIR>(tile, a.grp_bits[gi], a.grp_sorted[gi], tid, nitems, lp.ca, lp.sb);
+          xy_group_pass<XG_PAIR>(tile, a.grp_bits[gi], a.grp_sorted[gi], tid, nitems, lp.ca, lp.sb, nthr);
           e += 2;
         } else if (kind == XG_STAR2) {
-          xy_group_pass<XG_STAR2>(tile, a.grp_bits[gi], a.grp_sorted[gi], tid, nitems, lp.ca, lp.sb);
+          xy_group_pass<XG_STAR2>(tile, a.grp_bits[gi], a.grp_sorted[gi], tid, nitems, lp.ca, lp.sb, nthr);
           e += 2;
         } else {
-          xy_group_pass<XG_STAR3>(tile, a.grp_bits[gi], a.grp_sorted[gi], tid, nitems, lp.ca, lp.sb);
+          xy_group_pass<XG_STAR3>(tile, a.grp_bits[gi], a.grp_sorted[gi], tid, nitems, lp.ca, lp.sb, nthr);
           e += 3;
         }
         __syncthreads();
@@ -1358,7 +1356,7 @@ __global__ void __launch_bounds__(512) qaoa_xy_kernel(const XyArgs a) {
   for (int k = 0; k < E; ++k) S::store(psi, xb + g.goff[w][k], vr[k], vi[k]);
   if (sa.flags & F_EXPV) {
     __syncthreads();  // the tile buffer becomes reduction scratch
-    block_sum2(e_part, n_part, reinterpret_cast<double*>(smem_raw));
+    block_sum2(e_part, n_part, reinterpret_cast<double*>(smem_raw), nthr);
     if (tid == 0) {
       double* part = sa.partials + (uint64_t)set * sa.partials_stride;
       part[2 * (uint64_t)blockIdx.x] = e_part;
@@ -1371,6 +1369,7 @@ __global__ void __launch_bounds__(512) qaoa_xy_kernel(const XyArgs a) {
 // layer l's (beta term, gamma term) go to partials + l * layer_partials_stride.
 template <class S, class D, int EB>
 __global__ void __launch_bounds__(512) qaoa_adjoint_tile_kernel(const AdjArgs a) {
+  const uint32_t nthr = blockDim.x;
   constexpr int E = 1 << EB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   typename S::L* lds = reinterpret_cast<typename S::L*>(smem_raw);
@@ -1402,8 +1401,8 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_tile_kernel(const AdjArgs a)
       w = w_load;
     }
     __syncthreads();  // previous layer's table reads are done
-    undo_phase<D, EB>(vr, vi, lr, li, cv, a, lp, tab, tid, gacc);
-    block_sum2(xacc, gacc, scratch);
+    undo_phase<D, EB>(vr, vi, lr, li, cv, a, lp, tab, tid, gacc, nthr);
+    block_sum2(xacc, gacc, scratch, nthr);
     if (tid == 0) {
       a.partials[(uint64_t)l * a.layer_partials_stride] = xacc;
       a.partials[(uint64_t)l * a.layer_partials_stride + 1] = gacc;
@@ -1422,6 +1421,7 @@ __global__ void __launch_bounds__(512) qaoa_adjoint_tile_kernel(const AdjArgs a)
 // partials + l * layer_stride + s * blocks * 2 (the gamma term only in run 0).
 __global__ void __launch_bounds__(256) grad_finalize_kernel(const double* partials, int p, int nsw, uint64_t blocks,
                                                             uint64_t layer_stride, double* out) {
+  const uint32_t nthr = blockDim.x;
   __shared__ double scratch[16];
   const int l = blockIdx.x;
   const double* part = partials + (uint64_t)l * layer_stride;
@@ -1432,7 +1432,7 @@ __global__ void __launch_bounds__(256) grad_finalize_kernel(const double* partia
       xb += part[2 * (s * blocks + i)];
       gg += part[2 * (s * blocks + i) + 1];
     }
-  block_sum2(xb, gg, scratch);
+  block_sum2(xb, gg, scratch, nthr);
   if (threadIdx.x == 0) {
     out[1 + l] = 2.0 * gg;
     out[1 + p + l] = 2.0 * xb;
@@ -1448,13 +1448,14 @@ __global__ void __launch_bounds__(256) grad_finalize_kernel(const double* partia
 // state's partials and writes tmp[s * tstride + 2 b + {0,1}].  Fixed order.
 __global__ void __launch_bounds__(256) reduce_chunks_kernel(const double* partials, uint64_t count, uint64_t stride,
                                                             uint64_t per, double* tmp, uint64_t tstride) {
+  const uint32_t nthr = blockDim.x;
   __shared__ double scratch[16];
   const double* part = partials + (uint64_t)blockIdx.y * stride;
   const uint64_t lo = (uint64_t)blockIdx.x * per;
   const uint64_t hi = lo + per < count ? lo + per : count;
   double e = 0.0, q = 0.0;
   for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) { e += part[2 * i]; q += part[2 * i + 1]; }
-  block_sum2(e, q, scratch);
+  block_sum2(e, q, scratch, nthr);
   if (threadIdx.x == 0) {
     tmp[(uint64_t)blockIdx.y * tstride + 2 * blockIdx.x] = e;
     tmp[(uint64_t)blockIdx.y * tstride + 2 * blockIdx.x + 1] = q;
@@ -1464,11 +1465,12 @@ __global__ void __launch_bounds__(256) reduce_chunks_kernel(const double* partia
 // out[2 s + {0,1}] = fixed-order sum of set s's `count` partial pairs.
 __global__ void __launch_bounds__(256) finalize_batch_kernel(const double* partials, uint64_t count,
                                                              uint64_t stride, double* out) {
+  const uint32_t nthr = blockDim.x;
   __shared__ double scratch[16];
   const double* part = partials + (uint64_t)blockIdx.x * stride;
   double e = 0.0, q = 0.0;
   for (uint64_t i = threadIdx.x; i < count; i += blockDim.x) { e += part[2 * i]; q += part[2 * i + 1]; }
-  block_sum2(e, q, scratch);
+  block_sum2(e, q, scratch, nthr);
   if (threadIdx.x == 0) { out[2 * blockIdx.x] = e; out[2 * blockIdx.x + 1] = q; }
 }
 
@@ -1540,6 +1542,7 @@ __global__ void __launch_bounds__(512) fwht_sweep_kernel(const FwhtArgs a) {
 template <class S, class D>
 __global__ void __launch_bounds__(256) expectation_kernel(const void* psi, const void* diag, double offset,
                                                           uint64_t N, double* partials) {
+  const uint32_t nthr = blockDim.x;
   __shared__ double scratch[16];
   double e = 0.0, q = 0.0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -1550,15 +1553,16 @@ __global__ void __launch_bounds__(256) expectation_kernel(const void* psi, const
     e += pr * (D::get(diag, x) + offset);
     q += pr;
   }
-  block_sum2(e, q, scratch);
+  block_sum2(e, q, scratch, nthr);
   if (threadIdx.x == 0) { partials[2 * blockIdx.x] = e; partials[2 * blockIdx.x + 1] = q; }
 }
 
 __global__ void __launch_bounds__(256) finalize_kernel(const double* partials, uint64_t count, double* out) {
+  const uint32_t nthr = blockDim.x;
   __shared__ double scratch[16];
   double e = 0.0, q = 0.0;
   for (uint64_t i = threadIdx.x; i < count; i += blockDim.x) { e += partials[2 * i]; q += partials[2 * i + 1]; }
-  block_sum2(e, q, scratch);
+  block_sum2(e, q, scratch, nthr);
   if (threadIdx.x == 0) { out[0] = e; out[1] = q; }
 }
 
