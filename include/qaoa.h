@@ -154,7 +154,10 @@ int qaoa_precompute_diag(int n, int64_t num_terms, const double *w, const int64_
  * exactly representable angle (agreeing with the direct evaluation to a few
  * units in the last place of the angle); a workgroup holding other I32 values
  * takes the same three-entry product twice, over the value's bytes.  complex64
- * states are updated in double precision and rounded to float when stored.
+ * states are updated in single precision (phase-table entries rounded once from
+ * their double values), except in launches where a layer has |tan beta| > 64,
+ * which use double precision; E and sum |psi|^2 are accumulated in FP64.
+ * complex128 states are updated in double precision.
  * Results are deterministic (fixed reduction order).
  */
 int qaoa_evolve(int n, int p, const double *gamma, const double *beta,
