@@ -354,10 +354,6 @@ struct SweepArgs {
   int set0;
   int p_total;
   int layer0;
-  // complex64 sweeps: 1 = every layer of the launch allows FP32, 0 = some
-  // layer needs FP64 (decided on the host from its angles), -1 = decide in the
-  // kernel from the parameter rows (angles that live on the device)
-  int prec;
   uint64_t set_stride_bytes;
   uint64_t partials_stride;
 };
@@ -858,12 +854,9 @@ __global__ void __launch_bounds__(S::kMaxThreads, S::kMinWavesPerSimd) qaoa_swee
     // into scratch memory per lane for them.
     typedef __attribute__((address_space(4))) const SweepArgs KernArgs;
     const SweepArgs& a = *(const SweepArgs*)(KernArgs*)__builtin_amdgcn_kernarg_segment_ptr();
-    bool f32 = a.prec > 0;
-    if (a.prec < 0) {
-      const uint32_t set = blockIdx.y;
-      f32 = fabs(layer_params(a, set, 0).tn) <= kTanMaxF32;
-      if constexpr (FUSE) f32 = f32 && fabs(layer_params(a, set, 1).tn) <= kTanMaxF32;
-    }
+    const uint32_t set = blockIdx.y;
+    bool f32 = fabs(layer_params(a, set, 0).tn) <= kTanMaxF32;
+    if constexpr (FUSE) f32 = f32 && fabs(layer_params(a, set, 1).tn) <= kTanMaxF32;
     if (f32) sweep_tile<S, D, EB, INIT, PHASE, EXPV, FUSE, PLO, PHI, float, float2>(a);
     else sweep_tile<S, D, EB, INIT, PHASE, EXPV, FUSE, PLO, PHI, double, double2>(a);
   } else {

@@ -1250,12 +1250,6 @@ static int enqueue_evolve(int n, int p, int batch, const double* h_gamma, const 
         a.g = pl.sweeps[stp.sweep];
         a.layer0 = host_angles ? stp.layer - l0 : stp.layer;
         a.flags = stp.flags;
-        a.prec = -1;  // device angles: the kernel reads them
-        if (host_angles) {
-          bool f32 = std::fabs(std::tan(h_beta[stp.layer])) <= qk::kTanMaxF32;
-          if (stp.flags & qk::F_FUSE) f32 = f32 && std::fabs(std::tan(h_beta[stp.layer + 1])) <= qk::kTanMaxF32;
-          a.prec = f32 ? 1 : 0;
-        }
         last_blocks = plan_blocks(n, a.g);
         rc = launch_sweep(a, state_dtype, diag_dtype, pl.wide, last_blocks, sets, st);
         if (rc) return rc;
