@@ -577,7 +577,7 @@ def main(argv=None):
         return 0
 
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); the hot path is "
+        print(f"bench.py: measures one GPU only (--gpus {args.gpus} requested); the hot path is "
               "single-device and no multi-GPU path exists", file=sys.stderr)
         return 2
 

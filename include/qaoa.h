@@ -53,7 +53,7 @@ enum {
     QAOA_ERR_RANGE = 2,       /* cost values not representable in the requested dtype */
     QAOA_ERR_NOMEM = 3,       /* a caller-provided buffer is too small */
     QAOA_ERR_DEVICE = 4,      /* HIP runtime or launch failure (message has the HIP error) */
-    QAOA_ERR_UNSUPPORTED = 5  /* valid request this build does not implement */
+    QAOA_ERR_UNSUPPORTED = 5  /* valid request the library does not implement */
 };
 
 /* State dtypes (interleaved complex). */

@@ -1,6 +1,6 @@
 """Pins of the oracle's XY mixers (Section 3.2: M = sum over ring or complete-
 graph edges of (X_i X_j + Y_i Y_j)/2, one layer = the product of the two-qubit
-exponentials in a fixed edge order; the orders are this build's reading).
+exponentials in a fixed edge order; the paper leaves the order open, the one used here is a stated reading).
 
 The edge orders are written out here from their definition (not taken from the
 oracle), and every layer is compared with the product of scipy expm of dense
