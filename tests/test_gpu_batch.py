@@ -65,6 +65,36 @@ def test_batch_equals_singles_bitwise(q, n, dtype, ddt, batch, p):
             assert torch.equal(out[s], o), (spp, s)
 
 
+def test_batch_complex64_precision_switch(q):
+    """complex64 sets whose layers straddle the FP32 bound |tan beta| = 64 (and
+    beta = pi/2 exactly), several sets per launch with different choices: each
+    workgroup decides from its own set's parameter rows, so the batch equals the
+    single calls bitwise, and both match the oracle."""
+    q, _lib = q
+    n, p = 18, 3
+    diag, off = q.qaoa_precompute_diag(n, W.labs_terms(n), "u16", device="cuda")
+    bet = np.array([[0.3, 0.5, 0.7], [np.pi / 2, 0.4, np.arctan(63.9)], [np.arctan(64.1), np.pi / 2 + 0.01, 0.2],
+                    [np.arctan(63.9), -np.arctan(63.9), np.pi / 2 - 1e-3], [1.0, 1.2, 1.4]])
+    gam = np.tile(np.array([0.11, 0.23, 0.31]), (bet.shape[0], 1))
+    batch = bet.shape[0]
+    c = oracle.diag_labs(n).astype(np.float64)
+    for spp in (0, 2):
+        states = torch.empty(batch, 1 << n, dtype=torch.complex64, device="cuda")
+        out = torch.empty(batch, 2, dtype=torch.float64, device="cuda")
+        _lib.qaoa_evolve_batch(n, torch.from_numpy(gam).cuda(), torch.from_numpy(bet).cuda(), diag, states,
+                               init=True, diag_offset=off, out=out, sets_per_pass=spp)
+        got = states.cpu().numpy().astype(np.complex128)
+        o = out.cpu().numpy()
+        for s in range(batch):
+            psi, o1 = _single(q, n, gam[s], bet[s], diag, off, "complex64")
+            assert torch.equal(states[s], psi) and torch.equal(out[s], o1), (spp, s)
+            ref = oracle.evolve(n, c, gam[s], bet[s])
+            E, nrm = oracle.expectation(n, ref, c)
+            assert np.linalg.norm(got[s] - ref) <= 1e-5, (spp, s)
+            assert abs(o[s, 0] - E) <= 1e-5 * max(1.0, abs(E)), (spp, s)
+            assert abs(o[s, 1] - nrm) <= 1e-5, (spp, s)
+
+
 @pytest.mark.parametrize("n,dtype", [(12, "complex128"), (18, "complex64"), (19, "complex128")])
 def test_batch_matches_oracle(q, n, dtype):
     q, _lib = q
