@@ -261,7 +261,8 @@ def bench_batch(args):
             "single_path_evals_per_s": batch / (ms_single * 1e-3), "speedup_vs_single": ms_single / ms_batch,
             "eager_batch_evals_per_s": batch / t_batch_eager, "eager_single_evals_per_s": batch / t_single_eager,
             "roofline": {"bound": "hbm", "kernel": "qaoa_sweep_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": measured_traffic(f"{cfg['name']}_spp{spp}"),
                          "bytes_per_launch": sum(per_launch) * batch / launches, "launches_per_step": launches,
                          "avg_launch_ms": ms_batch / launches}}
 
